@@ -1,0 +1,193 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the smoke check.
+
+This module only draws and lays out inputs: the anisotropy tensor, the relaxation time and the
+initial density and velocity fields. It holds none of the method's arithmetic (no equilibrium,
+no moments, no tensor conversion), so the oracle and the HIP library can both be fed from it
+without sharing any computation.
+
+Conventions (identical for every consumer):
+
+* grid shape ``(nx, ny, nz)`` (``nz == 1`` for two-dimensional lattices), nodes at integer
+  positions ``0 .. n-1``, periodic on every face;
+* ``rho`` is a float64 array [N] and ``s`` a float64 array [d][N] with N = nz*ny*nx, x fastest;
+* ``tensor`` is a 3 x 3 float64 array (only the leading d x d block is used) of the given
+  ``tensor_kind``: ``"theta"`` = cs^2 A^-1 in lattice units (the equilibrium pressure tensor per
+  unit density), ``"A"`` = the matrix A of the anisotropic Maxwell-Boltzmann exponent, or
+  ``"Atilde"`` = an un-normalised multiple of A.
+
+The paper's own experiment (Sec. 4) uses no dataset: the Taylor-Green vortex below is analytic.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# Squared lattice speed of sound of the D2Q9 / D3Q19 / D3Q27 lattices (unit spacing and time
+# step); the workload definitions state their tensors as multiples of it.
+CS2 = 1.0 / 3.0
+
+DIMS = {"D2Q9": 2, "D3Q19": 3, "D3Q27": 3}
+
+
+@dataclass
+class Workload:
+    lattice: str
+    shape: tuple            # (nx, ny, nz)
+    tensor: np.ndarray      # 3 x 3
+    tensor_kind: str
+    tau: float
+    steps: int
+    rho: np.ndarray         # [N]
+    s: np.ndarray           # [d][N]
+    u0: float               # initial velocity amplitude (normalises velocity errors)
+    order: int = 3
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def d(self) -> int:
+        return DIMS[self.lattice]
+
+    @property
+    def cells(self) -> int:
+        return int(np.prod(self.shape))
+
+
+def grid(shape):
+    """Coordinate arrays x, y, z of shape [N] (x fastest)."""
+    nx, ny, nz = shape
+    z, y, x = np.meshgrid(np.arange(nz, dtype=np.float64), np.arange(ny, dtype=np.float64),
+                          np.arange(nx, dtype=np.float64), indexing="ij")
+    return x.reshape(-1), y.reshape(-1), z.reshape(-1)
+
+
+def pad3(t) -> np.ndarray:
+    t = np.asarray(t, dtype=np.float64)
+    out = np.zeros((3, 3))
+    out[: t.shape[0], : t.shape[1]] = t
+    return out
+
+
+def rotation_2d(deg: float) -> np.ndarray:
+    a = np.deg2rad(deg)
+    return np.array([[np.cos(a), -np.sin(a)], [np.sin(a), np.cos(a)]])
+
+
+def random_theta(seed: int, lo: float = 0.6, hi: float = 1.4) -> np.ndarray:
+    """Random SPD tensor cs^2 Q diag(lambda) Q^T, lambda ~ U[lo, hi], Q Haar-distributed.
+
+    Draw order (fixed): lambda, then the 3 x 3 normal matrix that QR turns into Q (signs fixed
+    by diag(R), det(Q) forced to +1).
+    """
+    rng = np.random.default_rng(seed)
+    lam = rng.uniform(lo, hi, 3)
+    g = rng.normal(size=(3, 3))
+    q, r = np.linalg.qr(g)
+    q = q * np.sign(np.diag(r))
+    if np.linalg.det(q) < 0:
+        q[:, 0] *= -1.0
+    return CS2 * (q @ np.diag(lam) @ q.T)
+
+
+def uniform_fields(shape, d, rho=1.0, s=None):
+    n = int(np.prod(shape))
+    r = np.full(n, float(rho))
+    v = np.zeros((d, n))
+    if s is not None:
+        for a in range(d):
+            v[a] = s[a]
+    return r, v
+
+
+def random_fields(shape, d, seed, amp_rho=0.01, amp_s=0.02):
+    """Smooth-free random fields (for conservation and permutation checks)."""
+    rng = np.random.default_rng(seed)
+    n = int(np.prod(shape))
+    return 1.0 + amp_rho * rng.uniform(-1, 1, n), amp_s * rng.uniform(-1, 1, (d, n))
+
+
+def shear_wave(shape, d, k_axis, u_axis, u0, mode=1):
+    """s_u = u0 sin(2 pi mode x_k / n_k), rho = 1."""
+    x = grid(shape)
+    n = int(np.prod(shape))
+    rho = np.ones(n)
+    s = np.zeros((d, n))
+    s[u_axis] = u0 * np.sin(2.0 * np.pi * mode * x[k_axis] / shape[k_axis])
+    return rho, s
+
+
+def density_wave(shape, d, axis, amp, mode=1):
+    """rho = 1 + amp cos(2 pi mode x_a / n_a), s = 0."""
+    x = grid(shape)
+    n = int(np.prod(shape))
+    return 1.0 + amp * np.cos(2.0 * np.pi * mode * x[axis] / shape[axis]), np.zeros((d, n))
+
+
+def taylor_green_2d(n, u0, kx_mult=1, ky_mult=1):
+    """Sec. 4 vortex on an n x n grid: eq:TG_u at t = 0, rho = 1 + 3 p(0) from eq:TG_p.
+
+    Readings: p0 = 0 and rho = 1 inside p; nodes at x = 0 .. n-1.
+    """
+    shape = (n, n, 1)
+    x, y, _ = grid(shape)
+    kx = 2.0 * np.pi * kx_mult / n
+    ky = 2.0 * np.pi * ky_mult / n
+    ux = -u0 * np.sqrt(ky / kx) * np.cos(kx * x) * np.sin(ky * y)
+    uy = u0 * np.sqrt(kx / ky) * np.cos(ky * y) * np.sin(kx * x)
+    p = -(u0 * u0 / 4.0) * ((ky / kx) * np.cos(2 * kx * x) + (kx / ky) * np.cos(2 * ky * y))
+    rho = 1.0 + 3.0 * p
+    return rho, np.stack([ux, uy])
+
+
+def taylor_green_3d(shape, u0):
+    """Standard 3-D Taylor-Green vortex with k = 2 pi / n per axis.
+
+    s = u0 (sin kx cos ky cos kz, -cos kx sin ky cos kz, 0),
+    p = (u0^2/16)(cos 2kx + cos 2ky)(cos 2kz + 2), rho = 1 + 3 p.
+    """
+    x, y, z = grid(shape)
+    kx, ky, kz = (2.0 * np.pi / shape[0], 2.0 * np.pi / shape[1], 2.0 * np.pi / shape[2])
+    sx = u0 * np.sin(kx * x) * np.cos(ky * y) * np.cos(kz * z)
+    sy = -u0 * np.cos(kx * x) * np.sin(ky * y) * np.cos(kz * z)
+    sz = np.zeros_like(sx)
+    p = (u0 * u0 / 16.0) * (np.cos(2 * kx * x) + np.cos(2 * ky * y)) * (np.cos(2 * kz * z) + 2.0)
+    return 1.0 + 3.0 * p, np.stack([sx, sy, sz])
+
+
+# ---- the workload configurations ----------------------------------------------------------
+
+def config1_theta() -> np.ndarray:
+    """cs^2 R(30 deg) diag(1.2, 0.8) R(30 deg)^T (2 x 2 block)."""
+    r = rotation_2d(30.0)
+    return pad3(CS2 * (r @ np.diag([1.2, 0.8]) @ r.T))
+
+
+def config1(n: int = 64, steps: int = 1000) -> Workload:
+    """D2Q9 n x n periodic, FP64, tau = 0.8, shear wave s_x = 0.01 sin(2 pi y / n)."""
+    shape = (n, n, 1)
+    rho, s = shear_wave(shape, 2, k_axis=1, u_axis=0, u0=0.01)
+    return Workload("D2Q9", shape, config1_theta(), "theta", 0.8, steps, rho, s, 0.01, name="d2q9_shear")
+
+
+def config2_theta(seed: int = 0) -> np.ndarray:
+    return random_theta(seed)
+
+
+def config2(n: int = 256, steps: int = 1000, seed: int = 0, lattice: str = "D3Q19", shape=None) -> Workload:
+    """D3Q19 n^3 periodic, seeded random SPD tensor, tau = 0.7, 3-D Taylor-Green u0 = 0.02."""
+    shape = tuple(shape) if shape is not None else (n, n, n)
+    rho, s = taylor_green_3d(shape, 0.02)
+    return Workload(lattice, shape, config2_theta(seed), "theta", 0.7, steps, rho, s, 0.02,
+                    name=f"{lattice.lower()}_tg", meta={"seed": seed})
+
+
+def config3_theta() -> np.ndarray:
+    return CS2 * np.diag([1.5, 1.0, 0.5])
+
+
+def e1_taylor_green(a_xy: float, order: int, n: int = 64) -> Workload:
+    """Sec. 4 experiment: D2Q9 64^2, tau = 1, u_max = 0.02, A~ = [[1, a], [a, 1]], 400 steps."""
+    rho, s = taylor_green_2d(n, 0.02)
+    t = pad3(np.array([[1.0, a_xy], [a_xy, 1.0]]))
+    return Workload("D2Q9", (n, n, 1), t, "Atilde", 1.0, 400, rho, s, 0.02, order=order, name="e1_tg")
