@@ -1,0 +1,221 @@
+#!/usr/bin/env python3
+"""Benchmark of the fused anisotropic-equilibrium BGK stream-collide step on one MI355X.
+
+Workload: D3Q19 256^3 periodic, FP32 deviations, seeded random SPD tensor (seed 0),
+tau = 0.7, 3-D Taylor-Green initial state u0 = 0.02 -- one "step" is one fused
+stream-and-collide pass over the whole grid. Prints ONE JSON line:
+
+  value        whole-job MLUPS (cells * steps / time / 1e6), inputs resident in HBM
+  roofline     the step kernel against the 8 TB/s HBM peak: achieved = algorithmic bytes per
+               launch (2 q sizeof(float) = 152 B per cell) / mean kernel time from HIP events
+               on the launch stream; traffic = HBM bytes per launch from rocprofv3 counters
+               (profiles/), null if the kernel source changed since they were taken
+  cpu_baseline the FP64 oracle on the host cores, a bounded sample of the same workload
+  variants     FP16 / BF16 shifted-deviation storage and FP64 storage of the same workload:
+               MLUPS, roofline fraction and the per-field error against the FP64 path
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-variants]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_GBPS = 8000.0  # MI355X HBM3E
+METRIC = "MLUPS & % of HBM peak, D3Q19 256^3 fp32 vs fp16-shifted; adjoint/fwd ratio"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_d3q19_f32_256.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2605_27004_amd", "csrc", "kernels.hip")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    return ap.parse_args()
+
+
+def kernel_sha():
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def traffic_per_launch():
+    """HBM bytes per step launch from the committed rocprofv3 counter summary, or None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha") != kernel_sha():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def timed_steps(sim, steps, warmup, torch):
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    stream = sim.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    sim.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3  # seconds
+
+
+def field_errors(a, b, u0):
+    """e(f), e(rho), e(s) of run a against reference run b (dicts of torch tensors)."""
+    ef = ((a["f"] - b["f"]).abs().max() / b["f"].abs().max()).item()
+    er = ((a["rho"] - b["rho"]).abs().max() / b["rho"].abs().max()).item()
+    es = ((a["s"] - b["s"]).abs().max() / u0).item()
+    return {"f": ef, "rho": er, "s": es}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
+              "(multi-GPU slab decomposition is a design, not an implementation).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2605_27004_amd as lbm
+    import workloads as W
+
+    torch.cuda.init()
+    wl = W.config2(n=args.n)
+    cells = wl.cells
+    q = 19
+
+    def make(storage):
+        p = lbm.make_params(wl.lattice, storage, wl.shape, wl.tensor, wl.tensor_kind, wl.tau, 3)
+        return lbm.Simulation(p, wl.rho, wl.s)
+
+    # ---- headline: FP32 storage ----
+    sim = make("f32")
+    secs = timed_steps(sim, args.steps, args.warmup, torch)
+    mlups = cells * args.steps / secs / 1e6
+    kernel_s = secs / args.steps
+    alg_bytes = 2 * q * 4 * cells
+    achieved = alg_bytes / kernel_s / 1e9
+    _, _, tot = sim.moments(fields=False)
+    del sim
+    torch.cuda.empty_cache()
+
+    # ---- plain copy kernel over the same bytes (practical ceiling) ----
+    nbytes = q * 4 * cells
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        lbm.lbm_stream_copy(dst, src, nbytes, stream.cuda_stream)
+    torch.cuda.synchronize()
+    reps = 20
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        lbm.lbm_stream_copy(dst, src, nbytes, stream.cuda_stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbps = 2 * nbytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+
+    line = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(kernel_s * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"D3Q19 {args.n}^3 periodic, FP32 shifted deviations, seeded SPD tensor "
+                               "(eigenvalues U[0.6,1.4] cs^2, seed 0), tau=0.7, 3-D Taylor-Green u0=0.02",
+                   "lattice": "D3Q19", "grid": list(wl.shape), "storage": "f32", "order": 3, "tau": wl.tau,
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_GBPS, 4), "traffic": traffic_per_launch(),
+                     "algorithmic_bytes_per_launch": alg_bytes, "kernel": "k_step<D3Q19, float, 3>",
+                     "copy_kernel_GBps": round(copy_gbps, 1), "frac_of_copy": round(achieved / copy_gbps, 4)},
+        "mass_total": tot[0],
+    }
+
+    # ---- storage variants: speed and error against the FP64 path at full size ----
+    if not args.no_variants:
+        def run_fields(storage, steps):
+            s_ = make(storage)
+            s_.step(steps)
+            rho, sv, _ = s_.moments()
+            out = {"f": s_.f64(), "rho": rho, "s": sv}
+            torch.cuda.synchronize()
+            return out
+
+        ref = run_fields("f64", wl.steps)
+        variants = {}
+        for storage, sz in (("f16", 2), ("bf16", 2), ("f64", 8)):
+            s_ = make(storage)
+            t_ = timed_steps(s_, min(args.steps, 500), args.warmup, torch)
+            n_ = min(args.steps, 500)
+            del s_
+            torch.cuda.empty_cache()
+            v = {"MLUPS": round(cells * n_ / t_ / 1e6, 1),
+                 "frac": round(2 * q * sz * cells / (t_ / n_) / 1e9 / PEAK_GBPS, 4)}
+            if storage != "f64":
+                got = run_fields(storage, wl.steps)
+                v["err_vs_f64_after_%d_steps" % wl.steps] = field_errors(got, ref, wl.u0)
+                del got
+                torch.cuda.empty_cache()
+            variants[storage + ("_shifted" if storage != "f64" else "")] = v
+        got = run_fields("f32", wl.steps)
+        variants["f32_shifted"] = {"err_vs_f64_after_%d_steps" % wl.steps: field_errors(got, ref, wl.u0)}
+        del got, ref
+        torch.cuda.empty_cache()
+        line["variants"] = variants
+    line["adjoint_fwd_ratio"] = None
+
+    # ---- CPU baseline: the FP64 oracle on a bounded sample of the same workload ----
+    if not args.no_cpu_baseline:
+        import oracle
+
+        ainv = oracle.tensor_to_ainv(wl.tensor, wl.tensor_kind, 3)
+        f = oracle.init(wl.lattice, wl.shape, ainv, wl.rho, wl.s)
+        t0 = time.perf_counter()
+        oracle.steps(wl.lattice, wl.shape, ainv, wl.tau, f, args.cpu_steps)
+        dt = time.perf_counter() - t0
+        del f
+        cpu_name = ""
+        try:
+            with open("/proc/cpuinfo") as fh:
+                for ln in fh:
+                    if ln.startswith("model name"):
+                        cpu_name = ln.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
+        line["cpu_baseline"] = {"value": round(cells * args.cpu_steps / dt / 1e6, 3), "unit": "MLUPS",
+                                "cores": oracle.num_threads(), "kind": "oracle",
+                                "sample": f"FP64 oracle, {args.cpu_steps} steps of the full {args.n}^3 D3Q19 "
+                                          f"workload (init excluded), {dt:.1f} s on {cpu_name}"}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,192 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) library for the BGK lattice Boltzmann update with the
+ * third-order anisotropic equilibrium of "Lattice Boltzmann Methods with Anisotropic
+ * Equilibrium Distributions" (arXiv 2605.27004).
+ *
+ * What the library evolves (the paper's problem statement):
+ *   f_i(t+1, x + c_i) = f_i(t, x) + (1/tau) [f^eq_i(t, x) - f_i(t, x)]            (eq:LBE_BGK)
+ * on a periodic Cartesian grid with D2Q9, D3Q19 or D3Q27 velocities (App. C), where
+ *   f^eq_i = w_i rho [1 + c_i.s/cs^2 + H2_i:(s s + cs^2 K)/(2 cs^4)
+ *                     + H3_i:(s s s + cs^2 (K s + K s + K s))/(6 cs^6)]     (eq:3rd_order_equilibrium)
+ *   K = A^-1 - I                                                                     (eq:K-term)
+ *   rho = sum_i f_i,  rho s = sum_i f_i c_i                    (eq:a0discrete_f, eq:a1discrete_f)
+ * with cs^2 = 1/3 and A the symmetric positive-definite matrix of the anisotropic
+ * Maxwell-Boltzmann exponent (eq:equil). Order 2 (the paper's comparison case, Sec. 4)
+ * drops the H3 term.
+ *
+ * Conventions shared by every call:
+ *  - Grid: nx * ny * nz cells (nz = 1 for D2Q9), x fastest; cell n = (z*ny + y)*nx + x.
+ *  - Velocity order: the canonical order returned by lbm_lattice_info (rest first, then
+ *    opposite pairs c_{2p-1} = -c_{2p}: axes, face diagonals, body diagonals).
+ *  - Fields: rho is FP64 [N]; s (lattice velocity) is FP64 [d][N] (structure of arrays).
+ *  - Populations are stored as deviations g_i = f_i - sigma_i from a constant shift sigma_i
+ *    (lbm_params.shift_kind) in the storage precision, structure of arrays [q][N].
+ *    The canonical state at integer t is the PRE-collision f_i(t, x) of eq:LBE_BGK; every
+ *    read-out call refers to it, whatever the library keeps internally.
+ *  - Device pointers are HIP device addresses owned by the caller; they must stay valid
+ *    for the lifetime of the context. The library allocates no device memory.
+ *  - Every call returns LBM_OK (0) or a negative LBM_ERR_* code; no exception crosses the
+ *    ABI. lbm_last_error() returns a thread-local message for the last failing call.
+ *    Parameter errors are detected on the host before any device work is enqueued.
+ *  - All device work is enqueued on the stream given to lbm_init (hipStream_t; NULL is the
+ *    default stream) and is asynchronous unless stated otherwise.
+ *  - A context is not thread-safe; distinct contexts may share a device and a stream.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------------------- */
+#define LBM_OK 0
+#define LBM_ERR_ARG (-1)         /* invalid argument (NULL, bad enum, bad size, ...)      */
+#define LBM_ERR_NOT_SPD (-2)     /* tensor not symmetric or not positive definite        */
+#define LBM_ERR_TAU (-3)         /* tau <= 1/2: eta = rho cs^2 (tau - 1/2) must be > 0   */
+#define LBM_ERR_ALIGN (-4)       /* a device buffer is not 256-byte aligned              */
+#define LBM_ERR_HIP (-5)         /* a HIP runtime call failed (message has its string)   */
+#define LBM_ERR_UNSUPPORTED (-6) /* valid request this build does not implement          */
+#define LBM_ERR_NONFINITE (-7)   /* a conservation total is NaN or infinite              */
+#define LBM_ERR_SIZE (-8)        /* grid too large for the library's 32-bit cell indices */
+
+/* ---- enumerations --------------------------------------------------------------------- */
+#define LBM_D2Q9 0
+#define LBM_D3Q19 1
+#define LBM_D3Q27 2
+
+#define LBM_F64 0  /* populations stored as FP64, arithmetic FP64                      */
+#define LBM_F32 1  /* populations stored as FP32, arithmetic FP32                      */
+#define LBM_F16 2  /* populations stored as IEEE half, arithmetic FP32                 */
+#define LBM_BF16 3 /* populations stored as bfloat16, arithmetic FP32                  */
+
+/* How lbm_params.tensor is to be read (d x d leading block of the 3 x 3 array). */
+#define LBM_TENSOR_THETA 0  /* tensor = cs^2 A^-1: the equilibrium's second central moment per
+                               unit density, rho cs^2 A^-1 being the pressure tensor (App. E,
+                               eq:NSprefinal). Used as given: no det normalisation.            */
+#define LBM_TENSOR_A 1      /* tensor = A of eq:equil, used as given (the paper asks det A = 1,
+                               Sec. 2.2; the update is defined for any SPD A).                 */
+#define LBM_TENSOR_ATILDE 2 /* tensor = A~ proportional to A; A = A~ / det(A~)^(1/d) (Sec. 4
+                               gives the d = 2 case A = A~ / sqrt(det A~)).                   */
+
+/* Shift sigma_i subtracted from the stored populations (g_i = f_i - sigma_i). */
+#define LBM_SHIFT_REST 0   /* sigma_i = rho0 r_i with r_i = f^eq_i(1, 0) = w_i (1 + H2_i:K/(2 cs^2)),
+                              the anisotropic rest equilibrium (recommended).               */
+#define LBM_SHIFT_WEIGHT 1 /* sigma_i = rho0 w_i (leaves the O(K) part of r_i in storage).  */
+
+typedef struct lbm_params {
+    int32_t lattice;     /* LBM_D2Q9 | LBM_D3Q19 | LBM_D3Q27                               */
+    int32_t storage;     /* LBM_F64 | LBM_F32 | LBM_F16 | LBM_BF16                          */
+    int32_t order;       /* 3 = the method (eq:3rd_order_equilibrium); 2 = without H3      */
+    int32_t tensor_kind; /* LBM_TENSOR_*                                                   */
+    int32_t shift_kind;  /* LBM_SHIFT_*                                                    */
+    int32_t flags;       /* reserved; must be 0                                            */
+    int64_t nx, ny, nz;  /* grid extents, each >= 1; nz == 1 for D2Q9; periodic on all faces */
+    double tensor[9];    /* 3 x 3 row-major; leading d x d block used; must be symmetric
+                            (|T - T^T| <= 1e-12 |T|) and positive definite                 */
+    double tau;          /* BGK relaxation time of eq:LBE_BGK, > 1/2                       */
+    double rho0;         /* reference density of the shift sigma_i, > 0 (usually 1)        */
+} lbm_params;
+
+/* Host-side quantities derived from lbm_params (lbm_prepare). All FP64. */
+typedef struct lbm_derived {
+    int32_t q, d;
+    double ainv[9];        /* A^-1, 3 x 3 row-major, zero outside the d x d block          */
+    double k[9];           /* K = A^-1 - I (eq:K-term), same layout                        */
+    double omega;          /* 1 / tau                                                      */
+    double nu;             /* kinematic shear viscosity cs^2 (tau - 1/2) (Sec. 3)          */
+    double rest[27];       /* r_i = f^eq_i(rho = 1, s = 0), canonical order                */
+    double shift[27];      /* sigma_i of the stored deviations                             */
+    double min_rest_ratio; /* min_i r_i / w_i; negative values mean some rest populations
+                              are negative (valid SPD tensors can do this; diagnostic only) */
+} lbm_derived;
+
+typedef struct lbm_ctx lbm_ctx; /* opaque; host-side metadata only */
+
+/* Canonical velocity set of a lattice (App. C; c in lattice units, cs^2 = 1/3).
+ * q, d: out (may be NULL). c: out [q][3] integers (may be NULL). w: out [q] weights (may be
+ * NULL). opp: out [q], index of -c_i (may be NULL). Host only; returns LBM_ERR_ARG for an
+ * unknown lattice. */
+int lbm_lattice_info(int32_t lattice, int32_t *q, int32_t *d, int32_t *c, double *w, int32_t *opp);
+
+/* Validate p and compute the derived quantities (host only, no device work).
+ * Errors: LBM_ERR_ARG (enums, extents, rho0, flags), LBM_ERR_TAU, LBM_ERR_NOT_SPD (symmetry
+ * or Cholesky failure of A^-1), LBM_ERR_SIZE. out may be NULL (validation only). */
+int lbm_prepare(const lbm_params *p, lbm_derived *out);
+
+/* Bytes of one population array: q * nx * ny * nz * sizeof(storage). -1 if p is invalid. */
+int64_t lbm_pop_bytes(const lbm_params *p);
+
+/* Bytes of device scratch lbm_init needs (reduction partials). -1 if p is invalid. */
+int64_t lbm_scratch_bytes(const lbm_params *p);
+
+/* Create a context and write the initial state f_i(0, x) = f^eq_i(rho0(x), s0(x)).
+ *   pop_a, pop_b: two device buffers of lbm_pop_bytes(p) each, 256-byte aligned, distinct;
+ *                 the library ping-pongs between them (their contents are its state).
+ *   scratch:      device buffer of lbm_scratch_bytes(p), 256-byte aligned.
+ *   rho0:         device FP64 [N] initial density (read during this call's device work).
+ *   s0:           device FP64 [d][N] initial lattice velocity.
+ *   mask:         must be NULL (solid cells are not supported by this build).
+ *   stream:       hipStream_t for all work of this context.
+ * On success *out receives the context (free with lbm_destroy). Asynchronous. */
+int lbm_init(lbm_ctx **out, const lbm_params *p, void *pop_a, void *pop_b, void *scratch, const double *rho0,
+             const double *s0, const uint8_t *mask, void *stream);
+
+/* Advance by nsteps >= 0 steps of eq:LBE_BGK: one fused kernel per step that gathers the
+ * streamed populations, forms rho and s, builds f^eq_i and relaxes with 1/tau.
+ * Asynchronous. */
+int lbm_step(lbm_ctx *ctx, int64_t nsteps);
+
+/* Moments of the current state (eq:a0discrete_f, eq:a1discrete_f).
+ *   rho:    device FP64 [N] or NULL;  s: device FP64 [d][N] or NULL.
+ *   totals: host FP64 [4] or NULL: sum_x rho, sum_x rho s_x, sum_x rho s_y, sum_x rho s_z
+ *           (the last zero for D2Q9), reduced on the device in FP64 in a fixed order
+ *           (bit-reproducible for a given grid). Passing totals synchronises the stream and
+ *           returns LBM_ERR_NONFINITE if any total is NaN or infinite. */
+int lbm_moments(lbm_ctx *ctx, double *rho, double *s, double *totals);
+
+/* Canonical pre-collision deviations g_i(t, x) = f_i(t, x) - sigma_i in the storage precision,
+ * device [q][N] (lbm_pop_bytes(p) bytes), for checkpointing. Exact (a permutation). */
+int lbm_get_populations(lbm_ctx *ctx, void *out);
+
+/* Restore the state from deviations in the layout of lbm_get_populations (exact inverse).
+ * The step counter is left unchanged. */
+int lbm_set_populations(lbm_ctx *ctx, const void *in);
+
+/* Canonical pre-collision populations f_i(t, x) = g_i + sigma_i in FP64, device [q][N]. */
+int lbm_get_f64(lbm_ctx *ctx, double *out);
+
+/* Steps taken since lbm_init (-1 if ctx is NULL). */
+int64_t lbm_time(const lbm_ctx *ctx);
+
+/* Override the step kernel's work-group shape (block_x * block_y <= 256, block_x a multiple
+ * of 64). Results do not depend on it (each cell is computed independently). */
+int lbm_set_launch(lbm_ctx *ctx, int32_t block_x, int32_t block_y);
+
+/* Gradient of an objective with respect to the tensor entries, tau and a per-cell mask.
+ * Not implemented by this build: always returns LBM_ERR_UNSUPPORTED. */
+typedef struct lbm_grad_spec {
+    int32_t objective; /* 0 = outlet mass flux, 1 = kinetic energy */
+    int32_t reserved;
+    int64_t nsteps, checkpoint_every, outlet_plane;
+} lbm_grad_spec;
+int lbm_grad(lbm_ctx *ctx, const lbm_grad_spec *spec, double *dtensor, double *dtau, double *dmask);
+
+/* Free a context (NULL is allowed). Does not touch the caller's buffers. */
+void lbm_destroy(lbm_ctx *ctx);
+
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char *lbm_last_error(void);
+
+/* Measurement aid: copy nbytes (a multiple of 16) from src to dst with the library's plain
+ * streaming copy kernel on stream; the reference for achievable HBM bandwidth. */
+int lbm_stream_copy(void *dst, const void *src, int64_t nbytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

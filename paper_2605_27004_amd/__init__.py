@@ -1,0 +1,306 @@
+"""MI355X (gfx950) lattice Boltzmann update with the third-order anisotropic equilibrium of
+"Lattice Boltzmann Methods with Anisotropic Equilibrium Distributions" (arXiv 2605.27004).
+
+Thin ctypes binding of the C ABI in ``include/lbm.h`` (``lib/liblbm.so``, built by
+``python -m paper_2605_27004_amd.build``). The functions keep the C names and only marshal
+arguments: every step of the update runs in the HIP kernels. PyTorch is used for device
+memory and streams only (:class:`Simulation`). Importing this package fails loudly when the
+library has not been built; there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "liblbm.so")
+
+# ---- constants (mirror include/lbm.h) ---------------------------------------------------
+LBM_OK = 0
+LBM_ERR_ARG = -1
+LBM_ERR_NOT_SPD = -2
+LBM_ERR_TAU = -3
+LBM_ERR_ALIGN = -4
+LBM_ERR_HIP = -5
+LBM_ERR_UNSUPPORTED = -6
+LBM_ERR_NONFINITE = -7
+LBM_ERR_SIZE = -8
+
+LBM_D2Q9, LBM_D3Q19, LBM_D3Q27 = 0, 1, 2
+LBM_F64, LBM_F32, LBM_F16, LBM_BF16 = 0, 1, 2, 3
+LBM_TENSOR_THETA, LBM_TENSOR_A, LBM_TENSOR_ATILDE = 0, 1, 2
+LBM_SHIFT_REST, LBM_SHIFT_WEIGHT = 0, 1
+
+LATTICES = {"D2Q9": LBM_D2Q9, "D3Q19": LBM_D3Q19, "D3Q27": LBM_D3Q27}
+STORAGES = {"f64": LBM_F64, "f32": LBM_F32, "f16": LBM_F16, "bf16": LBM_BF16}
+TENSOR_KINDS = {"theta": LBM_TENSOR_THETA, "A": LBM_TENSOR_A, "Atilde": LBM_TENSOR_ATILDE}
+SHIFTS = {"rest": LBM_SHIFT_REST, "weight": LBM_SHIFT_WEIGHT}
+STORAGE_BYTES = {LBM_F64: 8, LBM_F32: 4, LBM_F16: 2, LBM_BF16: 2}
+
+
+class lbm_params(ctypes.Structure):
+    _fields_ = [("lattice", ctypes.c_int32), ("storage", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("tensor_kind", ctypes.c_int32), ("shift_kind", ctypes.c_int32), ("flags", ctypes.c_int32),
+                ("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64),
+                ("tensor", ctypes.c_double * 9), ("tau", ctypes.c_double), ("rho0", ctypes.c_double)]
+
+
+class lbm_derived(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_int32), ("d", ctypes.c_int32), ("ainv", ctypes.c_double * 9),
+                ("k", ctypes.c_double * 9), ("omega", ctypes.c_double), ("nu", ctypes.c_double),
+                ("rest", ctypes.c_double * 27), ("shift", ctypes.c_double * 27), ("min_rest_ratio", ctypes.c_double)]
+
+
+class lbm_grad_spec(ctypes.Structure):
+    _fields_ = [("objective", ctypes.c_int32), ("reserved", ctypes.c_int32), ("nsteps", ctypes.c_int64),
+                ("checkpoint_every", ctypes.c_int64), ("outlet_plane", ctypes.c_int64)]
+
+
+class LBMError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"[{code}] {message}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2605_27004_amd.build` "
+                          "(there is no fallback implementation)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
+    ip32 = ctypes.POINTER(ctypes.c_int32)
+    sig = {
+        "lbm_lattice_info": (ctypes.c_int, [i32, ip32, ip32, ip32, dp, ip32]),
+        "lbm_prepare": (ctypes.c_int, [ctypes.POINTER(lbm_params), ctypes.POINTER(lbm_derived)]),
+        "lbm_pop_bytes": (i64, [ctypes.POINTER(lbm_params)]),
+        "lbm_scratch_bytes": (i64, [ctypes.POINTER(lbm_params)]),
+        "lbm_init": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(lbm_params), vp, vp, vp, vp, vp, vp, vp]),
+        "lbm_step": (ctypes.c_int, [vp, i64]),
+        "lbm_moments": (ctypes.c_int, [vp, vp, vp, dp]),
+        "lbm_get_populations": (ctypes.c_int, [vp, vp]),
+        "lbm_set_populations": (ctypes.c_int, [vp, vp]),
+        "lbm_get_f64": (ctypes.c_int, [vp, vp]),
+        "lbm_time": (i64, [vp]),
+        "lbm_set_launch": (ctypes.c_int, [vp, i32, i32]),
+        "lbm_grad": (ctypes.c_int, [vp, ctypes.POINTER(lbm_grad_spec), dp, dp, vp]),
+        "lbm_destroy": (None, [vp]),
+        "lbm_last_error": (ctypes.c_char_p, []),
+        "lbm_stream_copy": (ctypes.c_int, [vp, vp, i64, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def _check(rc: int) -> int:
+    if rc != LBM_OK:
+        raise LBMError(rc, lbm_last_error())
+    return rc
+
+
+def _ptr(x):
+    """Device or host address of a torch tensor, an int, or None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+# ---- the C ABI, one function each ---------------------------------------------------------
+
+def lbm_last_error() -> str:
+    return (_lib.lbm_last_error() or b"").decode()
+
+
+def lbm_lattice_info(lattice: int):
+    """(q, d, c [q][3] list, w [q] list, opp [q] list) in the library's canonical order."""
+    q, d = ctypes.c_int32(), ctypes.c_int32()
+    c = (ctypes.c_int32 * 81)()
+    w = (ctypes.c_double * 27)()
+    opp = (ctypes.c_int32 * 27)()
+    _check(_lib.lbm_lattice_info(lattice, ctypes.byref(q), ctypes.byref(d), c, w, opp))
+    n = q.value
+    return n, d.value, [list(c[3 * i: 3 * i + 3]) for i in range(n)], list(w[:n]), list(opp[:n])
+
+
+def make_params(lattice="D3Q19", storage="f32", shape=(1, 1, 1), tensor=None, tensor_kind="theta", tau=0.8,
+                order=3, rho0=1.0, shift="rest") -> lbm_params:
+    p = lbm_params()
+    p.lattice = LATTICES[lattice] if isinstance(lattice, str) else int(lattice)
+    p.storage = STORAGES[storage] if isinstance(storage, str) else int(storage)
+    p.order = int(order)
+    p.tensor_kind = TENSOR_KINDS[tensor_kind] if isinstance(tensor_kind, str) else int(tensor_kind)
+    p.shift_kind = SHIFTS[shift] if isinstance(shift, str) else int(shift)
+    p.flags = 0
+    nx, ny, nz = (tuple(shape) + (1, 1, 1))[:3]
+    p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
+    t = [1.0 / 3.0, 0, 0, 0, 1.0 / 3.0, 0, 0, 0, 1.0 / 3.0] if tensor is None else [float(v) for v in
+                                                                                      _flat9(tensor)]
+    for i in range(9):
+        p.tensor[i] = t[i]
+    p.tau = float(tau)
+    p.rho0 = float(rho0)
+    return p
+
+
+def _flat9(t):
+    rows = [list(r) for r in t]
+    out = [0.0] * 9
+    for a, r in enumerate(rows):
+        for b, v in enumerate(r):
+            out[3 * a + b] = float(v)
+    return out
+
+
+def lbm_prepare(p: lbm_params) -> lbm_derived:
+    out = lbm_derived()
+    _check(_lib.lbm_prepare(ctypes.byref(p), ctypes.byref(out)))
+    return out
+
+
+def lbm_pop_bytes(p: lbm_params) -> int:
+    n = _lib.lbm_pop_bytes(ctypes.byref(p))
+    if n < 0:
+        _check(_lib.lbm_prepare(ctypes.byref(p), None))
+    return n
+
+
+def lbm_scratch_bytes(p: lbm_params) -> int:
+    n = _lib.lbm_scratch_bytes(ctypes.byref(p))
+    if n < 0:
+        _check(_lib.lbm_prepare(ctypes.byref(p), None))
+    return n
+
+
+def lbm_init(p: lbm_params, pop_a, pop_b, scratch, rho0, s0, mask=None, stream=None) -> int:
+    ctx = ctypes.c_void_p()
+    _check(_lib.lbm_init(ctypes.byref(ctx), ctypes.byref(p), _ptr(pop_a), _ptr(pop_b), _ptr(scratch), _ptr(rho0),
+                         _ptr(s0), _ptr(mask), _ptr(stream)))
+    return ctx.value
+
+
+def lbm_step(ctx: int, nsteps: int) -> None:
+    _check(_lib.lbm_step(ctx, int(nsteps)))
+
+
+def lbm_moments(ctx: int, rho=None, s=None, want_totals: bool = True):
+    tot = (ctypes.c_double * 4)()
+    _check(_lib.lbm_moments(ctx, _ptr(rho), _ptr(s), tot if want_totals else None))
+    return list(tot) if want_totals else None
+
+
+def lbm_get_populations(ctx: int, out) -> None:
+    _check(_lib.lbm_get_populations(ctx, _ptr(out)))
+
+
+def lbm_set_populations(ctx: int, inp) -> None:
+    _check(_lib.lbm_set_populations(ctx, _ptr(inp)))
+
+
+def lbm_get_f64(ctx: int, out) -> None:
+    _check(_lib.lbm_get_f64(ctx, _ptr(out)))
+
+
+def lbm_time(ctx: int) -> int:
+    return int(_lib.lbm_time(ctx))
+
+
+def lbm_set_launch(ctx: int, block_x: int, block_y: int) -> None:
+    _check(_lib.lbm_set_launch(ctx, int(block_x), int(block_y)))
+
+
+def lbm_grad(ctx: int, spec: lbm_grad_spec, dtensor=None, dtau=None, dmask=None) -> None:
+    dt = (ctypes.c_double * 9)()
+    du = ctypes.c_double()
+    _check(_lib.lbm_grad(ctx, ctypes.byref(spec), dt, ctypes.byref(du), _ptr(dmask)))
+
+
+def lbm_destroy(ctx: int) -> None:
+    _lib.lbm_destroy(ctx)
+
+
+def lbm_stream_copy(dst, src, nbytes: int, stream=None) -> None:
+    _check(_lib.lbm_stream_copy(_ptr(dst), _ptr(src), int(nbytes), _ptr(stream)))
+
+
+# ---- convenience wrapper: torch owns the buffers ---------------------------------------------
+
+class Simulation:
+    """A context plus the torch device buffers it runs on.
+
+    ``rho`` is a float64 array-like [N] and ``s`` [d][N] (numpy or torch); the initial state is
+    f^eq(rho, s). Work goes to ``stream`` (a torch.cuda.Stream) or torch's current stream.
+    """
+
+    def __init__(self, params: lbm_params, rho, s, device="cuda", stream=None):
+        import torch
+
+        self.torch = torch
+        self.params = params
+        self.derived = lbm_prepare(params)
+        self.q, self.d = self.derived.q, self.derived.d
+        self.n = params.nx * params.ny * params.nz
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nbytes = lbm_pop_bytes(params)
+        # 256-byte aligned by the caching allocator
+        self.pop_a = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.pop_b = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.scratch = torch.empty(lbm_scratch_bytes(params), dtype=torch.uint8, device=self.device)
+        rho_t = torch.as_tensor(rho, dtype=torch.float64).reshape(self.n).to(self.device)
+        s_t = torch.as_tensor(s, dtype=torch.float64).reshape(self.d, self.n).to(self.device).contiguous()
+        torch.cuda.synchronize(self.device)
+        self.ctx = lbm_init(params, self.pop_a, self.pop_b, self.scratch, rho_t, s_t, None,
+                            self.stream.cuda_stream)
+        self.stream.synchronize()  # rho_t / s_t are read by the init kernel
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lbm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def t(self) -> int:
+        return lbm_time(self.ctx)
+
+    def step(self, nsteps: int = 1):
+        lbm_step(self.ctx, nsteps)
+        return self
+
+    def set_launch(self, block_x: int, block_y: int):
+        lbm_set_launch(self.ctx, block_x, block_y)
+
+    def moments(self, fields: bool = True):
+        """(rho [N], s [d][N], totals[4]) as torch float64 tensors on the device (fields=False
+        returns only the totals)."""
+        torch = self.torch
+        rho = torch.empty(self.n, dtype=torch.float64, device=self.device) if fields else None
+        s = torch.empty((self.d, self.n), dtype=torch.float64, device=self.device) if fields else None
+        tot = lbm_moments(self.ctx, rho, s, True)
+        return rho, s, tot
+
+    def f64(self):
+        """Canonical pre-collision populations f_i(t) as a float64 [q][N] device tensor."""
+        out = self.torch.empty((self.q, self.n), dtype=self.torch.float64, device=self.device)
+        lbm_get_f64(self.ctx, out)
+        return out
+
+    def get_populations(self):
+        out = self.torch.empty(lbm_pop_bytes(self.params), dtype=self.torch.uint8, device=self.device)
+        lbm_get_populations(self.ctx, out)
+        return out
+
+    def set_populations(self, buf):
+        lbm_set_populations(self.ctx, buf)

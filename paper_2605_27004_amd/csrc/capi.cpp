@@ -1,0 +1,447 @@
+// capi.cpp -- host side of the C ABI declared in include/lbm.h: parameter validation and
+// preparation, context bookkeeping and kernel launches. No device memory is allocated here.
+#include <hip/hip_runtime_api.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/lbm.h"
+#include "common.hpp"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int fail_hip(hipError_t e, const char *what)
+{
+    return fail(LBM_ERR_HIP, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+constexpr double kCs2 = 1.0 / 3.0;
+
+// ---- lattice tables in canonical order -------------------------------------------------
+
+struct LatticeTable {
+    int q, d, np;
+    int c[kMaxQ][3];
+    double w[kMaxQ];
+    int opp[kMaxQ];
+};
+
+template <int LAT> void fill_table(LatticeTable &t)
+{
+    using L = Lattice<LAT>;
+    t.q = L::Q;
+    t.d = L::D;
+    t.np = L::NP;
+    t.c[0][0] = t.c[0][1] = t.c[0][2] = 0;
+    t.w[0] = (double)L::w_rest / kWeightDen;
+    t.opp[0] = 0;
+    for (int p = 0; p < L::NP; ++p) {
+        const PairRow v = L::pair(p);
+        const int ip = 2 * p + 1, im = 2 * p + 2;
+        t.c[ip][0] = v.cx;
+        t.c[ip][1] = v.cy;
+        t.c[ip][2] = v.cz;
+        t.c[im][0] = -v.cx;
+        t.c[im][1] = -v.cy;
+        t.c[im][2] = -v.cz;
+        t.w[ip] = t.w[im] = (double)L::w_pair(p) / kWeightDen;
+        t.opp[ip] = im;
+        t.opp[im] = ip;
+    }
+}
+
+bool table_of(int lattice, LatticeTable &t)
+{
+    switch (lattice) {
+    case LBM_D2Q9: fill_table<kD2Q9>(t); return true;
+    case LBM_D3Q19: fill_table<kD3Q19>(t); return true;
+    case LBM_D3Q27: fill_table<kD3Q27>(t); return true;
+    default: return false;
+    }
+}
+
+int storage_bytes(int storage)
+{
+    switch (storage) {
+    case LBM_F64: return 8;
+    case LBM_F32: return 4;
+    case LBM_F16:
+    case LBM_BF16: return 2;
+    default: return 0;
+    }
+}
+
+// ---- small dense linear algebra (d <= 3) ----------------------------------------------------
+
+// Cholesky factor L (lower) of a symmetric d x d matrix; false unless positive definite.
+bool cholesky(int d, const double *m, double *l)
+{
+    std::memset(l, 0, sizeof(double) * 9);
+    for (int j = 0; j < d; ++j) {
+        double s = m[j * d + j];
+        for (int k = 0; k < j; ++k) s -= l[j * 3 + k] * l[j * 3 + k];
+        if (!(s > 0.0)) return false;
+        l[j * 3 + j] = std::sqrt(s);
+        for (int i = j + 1; i < d; ++i) {
+            double t = m[i * d + j];
+            for (int k = 0; k < j; ++k) t -= l[i * 3 + k] * l[j * 3 + k];
+            l[i * 3 + j] = t / l[j * 3 + j];
+        }
+    }
+    return true;
+}
+
+// Inverse of an SPD matrix from its Cholesky factor: M^-1 = L^-T L^-1 (d x d, stride d).
+void spd_inverse(int d, const double *l, double *inv)
+{
+    double li[9] = {0};  // L^-1, lower, stride 3
+    for (int j = 0; j < d; ++j) {
+        li[j * 3 + j] = 1.0 / l[j * 3 + j];
+        for (int i = j + 1; i < d; ++i) {
+            double t = 0.0;
+            for (int k = j; k < i; ++k) t -= l[i * 3 + k] * li[k * 3 + j];
+            li[i * 3 + j] = t / l[i * 3 + i];
+        }
+    }
+    for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) {
+            double t = 0.0;
+            for (int k = 0; k < d; ++k) t += li[k * 3 + a] * li[k * 3 + b];
+            inv[a * d + b] = t;
+        }
+}
+
+double det_from_cholesky(int d, const double *l)
+{
+    double p = 1.0;
+    for (int j = 0; j < d; ++j) p *= l[j * 3 + j];
+    return p * p;
+}
+
+struct Prepared {
+    lbm_derived dv;
+    LatticeTable lat;
+    int d, q, bytes;
+    uint32_t n;
+};
+
+int prepare(const lbm_params *p, Prepared &out)
+{
+    if (!p) return fail(LBM_ERR_ARG, "params is NULL");
+    if (!table_of(p->lattice, out.lat)) return fail(LBM_ERR_ARG, "unknown lattice %d", p->lattice);
+    const int d = out.lat.d, q = out.lat.q;
+    out.d = d;
+    out.q = q;
+    out.bytes = storage_bytes(p->storage);
+    if (!out.bytes) return fail(LBM_ERR_ARG, "unknown storage %d", p->storage);
+    if (p->order != 2 && p->order != 3) return fail(LBM_ERR_ARG, "order must be 2 or 3 (got %d)", p->order);
+    if (p->tensor_kind < LBM_TENSOR_THETA || p->tensor_kind > LBM_TENSOR_ATILDE)
+        return fail(LBM_ERR_ARG, "unknown tensor kind %d", p->tensor_kind);
+    if (p->shift_kind != LBM_SHIFT_REST && p->shift_kind != LBM_SHIFT_WEIGHT)
+        return fail(LBM_ERR_ARG, "unknown shift kind %d", p->shift_kind);
+    if (p->flags != 0) return fail(LBM_ERR_ARG, "flags must be 0");
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1)
+        return fail(LBM_ERR_ARG, "grid extents must be >= 1 (got %lld x %lld x %lld)", (long long)p->nx,
+                    (long long)p->ny, (long long)p->nz);
+    if (d == 2 && p->nz != 1) return fail(LBM_ERR_ARG, "D2Q9 needs nz == 1 (got %lld)", (long long)p->nz);
+    const double nd = (double)p->nx * (double)p->ny * (double)p->nz;
+    // 32-bit cell indices and 32-bit byte offsets inside each population plane
+    if (nd >= 2147483648.0 || nd * out.bytes >= 4294967296.0)
+        return fail(LBM_ERR_SIZE, "grid of %.0f cells exceeds the 2^31-cell / 4 GiB-per-plane limit", nd);
+    out.n = (uint32_t)(p->nx * p->ny * p->nz);
+    if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LBM_ERR_TAU, "tau must be > 1/2 (got %g)", p->tau);
+    if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) return fail(LBM_ERR_ARG, "rho0 must be > 0 (got %g)", p->rho0);
+
+    // tensor -> A^-1
+    double t[9], tmax = 0.0;
+    for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) {
+            t[a * d + b] = p->tensor[a * 3 + b];
+            if (!std::isfinite(t[a * d + b])) return fail(LBM_ERR_ARG, "tensor has a non-finite entry");
+            tmax = std::fmax(tmax, std::fabs(t[a * d + b]));
+        }
+    for (int a = 0; a < d; ++a)
+        for (int b = a + 1; b < d; ++b)
+            if (std::fabs(t[a * d + b] - t[b * d + a]) > 1e-12 * tmax)
+                return fail(LBM_ERR_NOT_SPD, "tensor is not symmetric (T[%d][%d] != T[%d][%d])", a, b, b, a);
+    double l[9], ainv[9];
+    if (!cholesky(d, t, l)) return fail(LBM_ERR_NOT_SPD, "tensor is not positive definite");
+    if (p->tensor_kind == LBM_TENSOR_THETA) {
+        for (int k = 0; k < d * d; ++k) ainv[k] = t[k] / kCs2;  // tensor = cs^2 A^-1
+    } else {
+        double scale = 1.0;
+        if (p->tensor_kind == LBM_TENSOR_ATILDE) scale = std::pow(det_from_cholesky(d, l), 1.0 / d);
+        double inv[9];
+        spd_inverse(d, l, inv);  // (A~)^-1 or A^-1
+        for (int k = 0; k < d * d; ++k) ainv[k] = inv[k] * scale;  // A^-1 = det^(1/d) A~^-1
+    }
+    // symmetrise exactly (the inverse is symmetric up to round-off)
+    for (int a = 0; a < d; ++a)
+        for (int b = a + 1; b < d; ++b) ainv[a * d + b] = ainv[b * d + a] = 0.5 * (ainv[a * d + b] + ainv[b * d + a]);
+
+    lbm_derived &dv = out.dv;
+    std::memset(&dv, 0, sizeof dv);
+    dv.q = q;
+    dv.d = d;
+    for (int a = 0; a < d; ++a)
+        for (int b = 0; b < d; ++b) {
+            dv.ainv[a * 3 + b] = ainv[a * d + b];
+            dv.k[a * 3 + b] = ainv[a * d + b] - (a == b ? 1.0 : 0.0);  // K = A^-1 - I
+        }
+    dv.omega = 1.0 / p->tau;
+    dv.nu = kCs2 * (p->tau - 0.5);
+    const double trk = dv.k[0] + dv.k[4] + dv.k[8];
+    dv.min_rest_ratio = 1e300;
+    for (int i = 0; i < q; ++i) {
+        double ckc = 0.0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) ckc += out.lat.c[i][a] * dv.k[a * 3 + b] * out.lat.c[i][b];
+        // r_i = f^eq_i(1, 0) = w_i (1 + H2_i:K / (2 cs^2)),  H2_i:K = c.K.c - cs^2 tr K
+        const double r = out.lat.w[i] * (1.0 + (ckc - kCs2 * trk) / (2.0 * kCs2));
+        dv.rest[i] = r;
+        dv.shift[i] = p->rho0 * (p->shift_kind == LBM_SHIFT_REST ? r : out.lat.w[i]);
+        dv.min_rest_ratio = std::fmin(dv.min_rest_ratio, r / out.lat.w[i]);
+    }
+    return LBM_OK;
+}
+
+template <typename C> StepConsts<C> consts_for(const lbm_params &p, const Prepared &pr)
+{
+    StepConsts<C> k;
+    std::memset(&k, 0, sizeof k);
+    const lbm_derived &dv = pr.dv;
+    k.omega = (C)dv.omega;
+    k.rho0 = (C)p.rho0;
+    k.k[0] = (C)dv.k[0];
+    k.k[1] = (C)dv.k[4];
+    k.k[2] = (C)dv.k[8];
+    k.k[3] = (C)dv.k[1];
+    k.k[4] = (C)dv.k[2];
+    k.k[5] = (C)dv.k[5];
+    const double trk = dv.k[0] + dv.k[4] + dv.k[8];
+    for (int pp = 0; pp <= pr.lat.np; ++pp) {
+        const int i = pp == 0 ? 0 : 2 * pp - 1;  // the + member of pair pp (or the rest)
+        double ckc = 0.0;
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) ckc += pr.lat.c[i][a] * dv.k[a * 3 + b] * pr.lat.c[i][b];
+        k.w[pp] = (C)pr.lat.w[i];
+        k.rest[pp] = (C)dv.rest[i];
+        k.eoff[pp] = (C)(p.rho0 * dv.rest[i] - dv.shift[i]);
+        k.a[pp] = (C)(3.0 + 4.5 * ckc - 1.5 * trk);
+        k.sigma[pp] = (C)dv.shift[i];
+    }
+    return k;
+}
+
+bool aligned256(const void *ptr) { return ((uintptr_t)ptr & 255u) == 0; }
+
+}  // namespace
+
+struct lbm_ctx {
+    lbm_params p;
+    Prepared pr;
+    Grid grid;
+    StepConsts<double> k64;
+    StepConsts<float> k32;
+    void *pop[2];
+    int cur;
+    double *scratch;
+    hipStream_t stream;
+    int64_t t;
+    int block_x, block_y;
+};
+
+extern "C" {
+
+int lbm_lattice_info(int32_t lattice, int32_t *q, int32_t *d, int32_t *c, double *w, int32_t *opp)
+{
+    LatticeTable t;
+    if (!table_of(lattice, t)) return fail(LBM_ERR_ARG, "unknown lattice %d", lattice);
+    if (q) *q = t.q;
+    if (d) *d = t.d;
+    for (int i = 0; i < t.q; ++i) {
+        if (c)
+            for (int a = 0; a < 3; ++a) c[3 * i + a] = t.c[i][a];
+        if (w) w[i] = t.w[i];
+        if (opp) opp[i] = t.opp[i];
+    }
+    return LBM_OK;
+}
+
+int lbm_prepare(const lbm_params *p, lbm_derived *out)
+{
+    Prepared pr;
+    const int rc = prepare(p, pr);
+    if (rc) return rc;
+    if (out) *out = pr.dv;
+    return LBM_OK;
+}
+
+int64_t lbm_pop_bytes(const lbm_params *p)
+{
+    Prepared pr;
+    if (prepare(p, pr)) return -1;
+    return (int64_t)pr.q * (int64_t)pr.n * pr.bytes;
+}
+
+int64_t lbm_scratch_bytes(const lbm_params *p)
+{
+    Prepared pr;
+    if (prepare(p, pr)) return -1;
+    Grid g{(int32_t)p->nx, (int32_t)p->ny, (int32_t)p->nz, pr.n};
+    // 4 partial sums per reduction block, then 4 totals, rounded up to 256 bytes
+    const int64_t bytes = 8 * (4 * (int64_t)moments_blocks(g) + 4);
+    return (bytes + 255) / 256 * 256;
+}
+
+int lbm_init(lbm_ctx **out, const lbm_params *p, void *pop_a, void *pop_b, void *scratch, const double *rho0,
+             const double *s0, const uint8_t *mask, void *stream)
+{
+    if (!out) return fail(LBM_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    Prepared pr;
+    int rc = prepare(p, pr);
+    if (rc) return rc;
+    if (mask) return fail(LBM_ERR_UNSUPPORTED, "solid masks are not supported by this build");
+    if (!pop_a || !pop_b || !scratch || !rho0 || !s0) return fail(LBM_ERR_ARG, "a device pointer is NULL");
+    if (pop_a == pop_b) return fail(LBM_ERR_ARG, "pop_a and pop_b must be distinct buffers");
+    if (!aligned256(pop_a) || !aligned256(pop_b) || !aligned256(scratch))
+        return fail(LBM_ERR_ALIGN, "population and scratch buffers must be 256-byte aligned");
+    lbm_ctx *c = new (std::nothrow) lbm_ctx;
+    if (!c) return fail(LBM_ERR_ARG, "out of host memory");
+    c->p = *p;
+    c->pr = pr;
+    c->grid = Grid{(int32_t)p->nx, (int32_t)p->ny, (int32_t)p->nz, pr.n};
+    c->k64 = consts_for<double>(*p, pr);
+    c->k32 = consts_for<float>(*p, pr);
+    c->pop[0] = pop_a;
+    c->pop[1] = pop_b;
+    c->cur = 0;
+    c->scratch = (double *)scratch;
+    c->stream = (hipStream_t)stream;
+    c->t = 0;
+    c->block_x = 64;
+    c->block_y = 4;
+    hipError_t e = launch_init(p->lattice, p->storage, p->order, c->grid, c->k64, rho0, s0, c->pop[0], c->stream);
+    if (e != hipSuccess) {
+        delete c;
+        return fail_hip(e, "init kernel launch");
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+int lbm_step(lbm_ctx *c, int64_t nsteps)
+{
+    if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
+    if (nsteps < 0) return fail(LBM_ERR_ARG, "nsteps must be >= 0");
+    for (int64_t s = 0; s < nsteps; ++s) {
+        hipError_t e = launch_step(c->p.lattice, c->p.storage, c->p.order, c->grid, c->k64, c->k32, c->pop[c->cur],
+                                   c->pop[c->cur ^ 1], c->block_x, c->block_y, c->stream);
+        if (e != hipSuccess) return fail_hip(e, "step kernel launch");
+        c->cur ^= 1;
+        ++c->t;
+    }
+    return LBM_OK;
+}
+
+int lbm_moments(lbm_ctx *c, double *rho, double *s, double *totals)
+{
+    if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
+    const uint32_t nb = moments_blocks(c->grid);
+    double *partials = c->scratch;
+    double *dtot = c->scratch + 4 * (size_t)nb;
+    hipError_t e = launch_moments(c->p.lattice, c->p.storage, c->grid, c->k64, c->pop[c->cur], rho, s, partials,
+                                  dtot, c->stream);
+    if (e != hipSuccess) return fail_hip(e, "moments kernel launch");
+    if (!totals) return LBM_OK;
+    double h[4];
+    e = hipMemcpyAsync(h, dtot, sizeof h, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return fail_hip(e, "moments read-back");
+    // sum_x rho = N rho0 + sum_x (rho - rho0); the device sums the deviations
+    totals[0] = (double)c->grid.n * c->p.rho0 + h[0];
+    totals[1] = h[1];
+    totals[2] = h[2];
+    totals[3] = c->pr.d == 3 ? h[3] : 0.0;
+    for (int m = 0; m < 4; ++m)
+        if (!std::isfinite(totals[m])) return fail(LBM_ERR_NONFINITE, "conservation total %d is not finite", m);
+    return LBM_OK;
+}
+
+int lbm_get_populations(lbm_ctx *c, void *out)
+{
+    if (!c || !out) return fail(LBM_ERR_ARG, "NULL argument");
+    hipError_t e = launch_permute(c->p.lattice, c->p.storage, 0, c->grid, c->k64, c->pop[c->cur], out, c->stream);
+    return e == hipSuccess ? LBM_OK : fail_hip(e, "export kernel launch");
+}
+
+int lbm_set_populations(lbm_ctx *c, const void *in)
+{
+    if (!c || !in) return fail(LBM_ERR_ARG, "NULL argument");
+    hipError_t e = launch_permute(c->p.lattice, c->p.storage, 1, c->grid, c->k64, in, c->pop[c->cur], c->stream);
+    return e == hipSuccess ? LBM_OK : fail_hip(e, "import kernel launch");
+}
+
+int lbm_get_f64(lbm_ctx *c, double *out)
+{
+    if (!c || !out) return fail(LBM_ERR_ARG, "NULL argument");
+    hipError_t e = launch_permute(c->p.lattice, c->p.storage, 2, c->grid, c->k64, c->pop[c->cur], out, c->stream);
+    return e == hipSuccess ? LBM_OK : fail_hip(e, "export kernel launch");
+}
+
+int64_t lbm_time(const lbm_ctx *c) { return c ? c->t : -1; }
+
+int lbm_set_launch(lbm_ctx *c, int32_t block_x, int32_t block_y)
+{
+    if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
+    if (block_x < 64 || block_x % 64 != 0 || block_y < 1 || block_x * block_y > 256)
+        return fail(LBM_ERR_ARG, "block shape %d x %d: need block_x a multiple of 64 and block_x*block_y <= 256",
+                    block_x, block_y);
+    c->block_x = block_x;
+    c->block_y = block_y;
+    return LBM_OK;
+}
+
+int lbm_grad(lbm_ctx *c, const lbm_grad_spec *spec, double *dtensor, double *dtau, double *dmask)
+{
+    (void)c;
+    (void)spec;
+    (void)dtensor;
+    (void)dtau;
+    (void)dmask;
+    return fail(LBM_ERR_UNSUPPORTED, "lbm_grad is not implemented by this build");
+}
+
+void lbm_destroy(lbm_ctx *c) { delete c; }
+
+const char *lbm_last_error(void) { return g_last_error.c_str(); }
+
+int lbm_stream_copy(void *dst, const void *src, int64_t nbytes, void *stream)
+{
+    if (!dst || !src || nbytes < 0 || nbytes % 16 != 0)
+        return fail(LBM_ERR_ARG, "copy needs non-NULL buffers and a byte count that is a multiple of 16");
+    hipError_t e = launch_copy(dst, src, nbytes, (hipStream_t)stream);
+    return e == hipSuccess ? LBM_OK : fail_hip(e, "copy kernel launch");
+}
+
+}  // extern "C"

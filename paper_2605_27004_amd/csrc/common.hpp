@@ -1,0 +1,63 @@
+// common.hpp -- types shared by the host side of the C ABI and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+
+#include "lattice.hpp"
+
+namespace lbm {
+
+enum StorageId : int { kF64 = 0, kF32 = 1, kF16 = 2, kBF16 = 3 };
+
+// Per-step constants in the arithmetic precision C, passed by value as a kernel argument
+// (they land in scalar registers). Index 0 of the per-pair arrays is the rest velocity.
+//
+// With u = c.s, k = c.(K s) and |s|^2 for one velocity, the equilibrium in lattice units
+// (cs^2 = 1/3) splits as f^eq = rho r + w rho P'(s) with the rest part r = w (1 + 1.5 c.K.c
+// - 0.5 tr K) and the velocity part
+//     P'(s) = [4.5 u^2 - 1.5 |s|^2]                               (even in c)
+//           + [u (A_p - 4.5 |s|^2 + 4.5 u^2) - 3 k]               (odd in c, order 3)
+//           + [3 u]                                               (odd in c, order 2)
+// where A_p = 3 + 4.5 c.K.c - 1.5 tr K. The stored deviation is g = f - sigma, so
+//     g^eq = r (rho - rho0) + (rho0 r - sigma) + w rho P'(s).
+template <typename C> struct StepConsts {
+    C omega;            // 1 / tau
+    C rho0;             // reference density of the shift
+    C k[6];             // K_xx, K_yy, K_zz, K_xy, K_xz, K_yz
+    C w[kMaxPairs + 1];     // weight w_p
+    C rest[kMaxPairs + 1];  // r_p
+    C eoff[kMaxPairs + 1];  // rho0 r_p - sigma_p (zero for the rest-equilibrium shift)
+    C a[kMaxPairs + 1];     // A_p of the odd part (order 3)
+    C sigma[kMaxPairs + 1]; // sigma_p (read-out only)
+};
+
+struct Grid {
+    int32_t nx, ny, nz;
+    uint32_t n;  // cells = nx * ny * nz (< 2^31)
+};
+
+// ---- launchers (kernels.hip) -----------------------------------------------------------
+// All return hipSuccess or the launch error; they enqueue on `stream` and never synchronise.
+
+hipError_t launch_init(int lattice, int storage, int order, const Grid &g, const StepConsts<double> &k,
+                       const double *rho, const double *s, void *dst, hipStream_t stream);
+
+hipError_t launch_step(int lattice, int storage, int order, const Grid &g, const StepConsts<double> &k64,
+                       const StepConsts<float> &k32, const void *src, void *dst, int block_x, int block_y,
+                       hipStream_t stream);
+
+// rho / s may be null. partials: scratch of 4 * nblocks doubles; totals: 4 doubles of scratch.
+hipError_t launch_moments(int lattice, int storage, const Grid &g, const StepConsts<double> &k, const void *src,
+                          double *rho, double *s, double *partials, double *totals, hipStream_t stream);
+uint32_t moments_blocks(const Grid &g);
+
+// mode 0: out[i][x] = state[i][x - c_i] (raw storage type), mode 1: the inverse scatter,
+// mode 2: out[i][x] = double(state[i][x - c_i]) + sigma_i.
+hipError_t launch_permute(int lattice, int storage, int mode, const Grid &g, const StepConsts<double> &k,
+                          const void *src, void *dst, hipStream_t stream);
+
+hipError_t launch_copy(void *dst, const void *src, int64_t nbytes, hipStream_t stream);
+
+}  // namespace lbm

@@ -1,0 +1,484 @@
+// kernels.hip -- gfx950 kernels of the anisotropic-equilibrium BGK lattice Boltzmann update.
+//
+// State layout. Populations live in two structure-of-arrays buffers [q][nz][ny][nx] (x
+// fastest) of deviations g_i = f_i - sigma_i in the storage type S. After k steps the
+// current buffer holds the POST-collision values of step k-1 at their own cell, so the
+// canonical pre-collision state is the gather f_i(k, x) = sigma_i + state[i][x - c_i]
+// (periodic wrap). One step is therefore a single pass over HBM: gather q values along
+// -c_i (pull streaming), form rho and s, build the equilibrium, relax, and store q values
+// at the cell itself into the other buffer (eq:LBE_BGK). The initial state is written to
+// the same gather positions, and every read-out applies the same gather, so no
+// separate streaming pass exists anywhere.
+//
+// Equilibrium (eq:3rd_order_equilibrium with cs^2 = 1/3, per opposite pair c / -c):
+//   f^eq = rho r + w rho P'(s),  r = w (1 + 1.5 c.K.c - 0.5 tr K),
+//   P'   = 4.5 u^2 - 1.5 |s|^2  +/-  [u (A - 4.5 |s|^2 + 4.5 u^2) - 3 c.(K s)]   (order 3)
+//   P'   = 4.5 u^2 - 1.5 |s|^2  +/-  3 u                                         (order 2)
+// with u = c.s and A = 3 + 4.5 c.K.c - 1.5 tr K; the odd part changes sign between the two
+// members of a pair, the even part and r do not. The arithmetic runs on the stored
+// deviations, rho = rho0 + sum_i g_i and rho s = sum_i g_i c_i (sum_i sigma_i c_i = 0), which
+// keeps FP32 mass conservation at round-off of the deviations rather than of f.
+//
+// The path is bound by HBM bandwidth (2 q sizeof(S) bytes per cell update), so there is no
+// LDS and no MFMA: each lane owns one cell, loads are coalesced along x, and the periodic
+// wrap is a per-lane offset select.
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace lbm {
+namespace {
+
+// ---- storage conversions ---------------------------------------------------------------
+
+struct bf16_t {
+    uint16_t bits;
+};
+
+template <typename S> struct Conv;
+template <> struct Conv<double> {
+    using C = double;
+    __device__ static double ld(double v) { return v; }
+    __device__ static double st(double v) { return v; }
+};
+template <> struct Conv<float> {
+    using C = float;
+    __device__ static float ld(float v) { return v; }
+    __device__ static float st(float v) { return v; }
+};
+template <> struct Conv<_Float16> {
+    using C = float;
+    __device__ static float ld(_Float16 v) { return (float)v; }
+    __device__ static _Float16 st(float v) { return (_Float16)v; }  // round to nearest even
+};
+template <> struct Conv<bf16_t> {
+    using C = float;
+    __device__ static float ld(bf16_t v) { return __uint_as_float((uint32_t)v.bits << 16); }
+    __device__ static bf16_t st(float v)
+    {
+        // round to nearest even; NaN stays NaN
+        uint32_t u = __float_as_uint(v);
+        if ((u & 0x7fffffffu) > 0x7f800000u) return bf16_t{(uint16_t)((u >> 16) | 0x40u)};
+        u += 0x7fffu + ((u >> 16) & 1u);
+        return bf16_t{(uint16_t)(u >> 16)};
+    }
+};
+
+// ---- neighbourhood ---------------------------------------------------------------------
+
+// Offsets (in cells) from a cell to its periodic neighbours at coordinate -1 and +1 along
+// one axis.
+struct AxisOff {
+    int32_t m1, p1;
+};
+
+__device__ inline AxisOff axis_off(int32_t v, int32_t n, int32_t stride)
+{
+    AxisOff o;
+    o.m1 = (v == 0) ? (n - 1) * stride : -stride;
+    o.p1 = (v == n - 1) ? -(n - 1) * stride : stride;
+    return o;
+}
+
+// Offset to the cell x - c for one velocity component c in {-1, 0, 1} (a constant after
+// unrolling).
+__device__ inline int32_t back(const AxisOff &o, int c) { return c > 0 ? o.m1 : (c < 0 ? o.p1 : 0); }
+
+struct Cell {
+    uint32_t own;
+    AxisOff ox, oy, oz;
+};
+
+__device__ inline Cell cell_of(const Grid &g, int32_t x, int32_t y, int32_t z)
+{
+    Cell c;
+    c.own = (uint32_t)((z * g.ny + y) * g.nx + x);
+    c.ox = axis_off(x, g.nx, 1);
+    c.oy = axis_off(y, g.ny, g.nx);
+    c.oz = axis_off(z, g.nz, g.nx * g.ny);
+    return c;
+}
+
+template <int LAT> __device__ inline uint32_t src_plus(const Cell &c, int p)
+{
+    const PairRow v = Lattice<LAT>::pair(p);
+    return c.own + (uint32_t)(back(c.ox, v.cx) + back(c.oy, v.cy) + back(c.oz, v.cz));
+}
+
+template <int LAT> __device__ inline uint32_t src_minus(const Cell &c, int p)
+{
+    const PairRow v = Lattice<LAT>::pair(p);
+    return c.own + (uint32_t)(back(c.ox, -v.cx) + back(c.oy, -v.cy) + back(c.oz, -v.cz));
+}
+
+// Element `idx` of population plane i; plane bases are wave-uniform and the per-lane offset
+// stays a 32-bit byte offset (planes are < 4 GiB).
+template <typename S> __device__ inline const S *plane(const S *base, int i, uint32_t n)
+{
+    return base + (size_t)i * n;
+}
+template <typename S> __device__ inline S *plane(S *base, int i, uint32_t n) { return base + (size_t)i * n; }
+
+template <typename S> __device__ inline S ld_at(const S *p, uint32_t idx)
+{
+    return *reinterpret_cast<const S *>(reinterpret_cast<const char *>(p) + (uint32_t)(idx * (uint32_t)sizeof(S)));
+}
+template <typename S> __device__ inline void st_at(S *p, uint32_t idx, S v)
+{
+    *reinterpret_cast<S *>(reinterpret_cast<char *>(p) + (uint32_t)(idx * (uint32_t)sizeof(S))) = v;
+}
+
+// ---- the collision -----------------------------------------------------------------------
+
+// Equilibrium deviations g^eq = f^eq - sigma of every direction for one cell with density
+// rho = rho0 + drho and lattice velocity s: eqp[0] is the rest velocity, eqp[p+1] / eqm[p+1]
+// are the +c / -c members of pair p.
+template <int LAT, int ORDER, typename C>
+__device__ inline void equilibrium_pairs(const StepConsts<C> &k, C drho, C rho, C sx, C sy, C sz, C *eqp, C *eqm)
+{
+    using L = Lattice<LAT>;
+    const C usq = sx * sx + sy * sy + sz * sz;
+    const C ksx = k.k[0] * sx + k.k[3] * sy + k.k[4] * sz;
+    const C ksy = k.k[3] * sx + k.k[1] * sy + k.k[5] * sz;
+    const C ksz = k.k[4] * sx + k.k[5] * sy + k.k[2] * sz;
+    const C even0 = C(-1.5) * usq;
+    const C bq = C(-4.5) * usq;
+    eqp[0] = k.rest[0] * drho + k.eoff[0] + k.w[0] * rho * even0;
+#pragma unroll
+    for (int p = 0; p < L::NP; ++p) {
+        const PairRow v = L::pair(p);
+        C u = C(0), kc = C(0);
+        if (v.cx) { u += v.cx * sx; kc += v.cx * ksx; }
+        if (v.cy) { u += v.cy * sy; kc += v.cy * ksy; }
+        if (v.cz) { u += v.cz * sz; kc += v.cz * ksz; }
+        const C u2 = u * u;
+        const C even = C(4.5) * u2 + even0;
+        C odd;
+        if constexpr (ORDER == 3) {
+            odd = u * (k.a[p + 1] + bq + C(4.5) * u2) - C(3) * kc;
+        } else {
+            odd = C(3) * u;
+        }
+        const C wr = k.w[p + 1] * rho;
+        const C base = k.rest[p + 1] * drho + k.eoff[p + 1];
+        eqp[p + 1] = base + wr * (even + odd);
+        eqm[p + 1] = base + wr * (even - odd);
+    }
+}
+
+template <int LAT, typename C> __device__ inline void moments_of(const C *gp, const C *gm, C &drho, C &jx, C &jy, C &jz)
+{
+    using L = Lattice<LAT>;
+    drho = gp[0];
+    jx = C(0);
+    jy = C(0);
+    jz = C(0);
+#pragma unroll
+    for (int p = 0; p < L::NP; ++p) {
+        const PairRow v = L::pair(p);
+        drho += gp[p + 1] + gm[p + 1];
+        const C dif = gp[p + 1] - gm[p + 1];
+        if (v.cx > 0) jx += dif;
+        if (v.cx < 0) jx -= dif;
+        if (v.cy > 0) jy += dif;
+        if (v.cy < 0) jy -= dif;
+        if (v.cz > 0) jz += dif;
+        if (v.cz < 0) jz -= dif;
+    }
+}
+
+// ---- kernels -------------------------------------------------------------------------------
+
+template <int LAT, typename S, int ORDER>
+__global__ __launch_bounds__(256) void k_step(const S *__restrict__ src, S *__restrict__ dst, const Grid g,
+                                              const StepConsts<typename Conv<S>::C> k)
+{
+    using L = Lattice<LAT>;
+    using C = typename Conv<S>::C;
+    constexpr int NP = L::NP;
+    const int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int32_t z = blockIdx.z;
+    if (x >= g.nx || y >= g.ny) return;
+    const Cell c = cell_of(g, x, y, z);
+
+    C gp[NP + 1], gm[NP + 1];
+    gp[0] = Conv<S>::ld(ld_at(plane(src, 0, g.n), c.own));
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        gp[p + 1] = Conv<S>::ld(ld_at(plane(src, 2 * p + 1, g.n), src_plus<LAT>(c, p)));
+        gm[p + 1] = Conv<S>::ld(ld_at(plane(src, 2 * p + 2, g.n), src_minus<LAT>(c, p)));
+    }
+
+    C drho, jx, jy, jz;
+    moments_of<LAT>(gp, gm, drho, jx, jy, jz);
+    const C rho = k.rho0 + drho;
+    const C inv = C(1) / rho;
+    C eqp[NP + 1], eqm[NP + 1];
+    equilibrium_pairs<LAT, ORDER, C>(k, drho, rho, jx * inv, jy * inv, jz * inv, eqp, eqm);
+
+    st_at(plane(dst, 0, g.n), c.own, Conv<S>::st(gp[0] + k.omega * (eqp[0] - gp[0])));
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        st_at(plane(dst, 2 * p + 1, g.n), c.own, Conv<S>::st(gp[p + 1] + k.omega * (eqp[p + 1] - gp[p + 1])));
+        st_at(plane(dst, 2 * p + 2, g.n), c.own, Conv<S>::st(gm[p + 1] + k.omega * (eqm[p + 1] - gm[p + 1])));
+    }
+}
+
+// f_i(0, x) = f^eq_i(rho(x), s(x)) in FP64, stored as a deviation at the gather position
+// x - c_i of the current buffer.
+template <int LAT, typename S, int ORDER>
+__global__ __launch_bounds__(256) void k_init(const double *__restrict__ rho_in, const double *__restrict__ s_in,
+                                              S *__restrict__ dst, const Grid g, const StepConsts<double> k)
+{
+    using L = Lattice<LAT>;
+    constexpr int NP = L::NP;
+    const int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int32_t z = blockIdx.z;
+    if (x >= g.nx || y >= g.ny) return;
+    const Cell c = cell_of(g, x, y, z);
+    const double rho = rho_in[c.own];
+    const double sx = s_in[c.own];
+    const double sy = s_in[(size_t)g.n + c.own];
+    const double sz = (L::D == 3) ? s_in[2 * (size_t)g.n + c.own] : 0.0;
+    double eqp[NP + 1], eqm[NP + 1];
+    equilibrium_pairs<LAT, ORDER, double>(k, rho - k.rho0, rho, sx, sy, sz, eqp, eqm);
+    st_at(plane(dst, 0, g.n), c.own, Conv<S>::st((typename Conv<S>::C)eqp[0]));
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        st_at(plane(dst, 2 * p + 1, g.n), src_plus<LAT>(c, p), Conv<S>::st((typename Conv<S>::C)eqp[p + 1]));
+        st_at(plane(dst, 2 * p + 2, g.n), src_minus<LAT>(c, p), Conv<S>::st((typename Conv<S>::C)eqm[p + 1]));
+    }
+}
+
+constexpr int kRedThreads = 256;
+
+// Moments of the canonical state in FP64 plus per-block partial sums of (drho, jx, jy, jz)
+// in a fixed tree order.
+template <int LAT, typename S>
+__global__ __launch_bounds__(kRedThreads) void k_moments(const S *__restrict__ src, double *__restrict__ rho_out,
+                                                         double *__restrict__ s_out, double *__restrict__ partials,
+                                                         const Grid g, const double rho0)
+{
+    using L = Lattice<LAT>;
+    constexpr int NP = L::NP;
+    __shared__ double red[4][kRedThreads];
+    const int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int32_t z = blockIdx.z;
+    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+    if (x < g.nx && y < g.ny) {
+        const Cell c = cell_of(g, x, y, z);
+        double gp[NP + 1], gm[NP + 1];
+        gp[0] = (double)Conv<S>::ld(ld_at(plane(src, 0, g.n), c.own));
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            gp[p + 1] = (double)Conv<S>::ld(ld_at(plane(src, 2 * p + 1, g.n), src_plus<LAT>(c, p)));
+            gm[p + 1] = (double)Conv<S>::ld(ld_at(plane(src, 2 * p + 2, g.n), src_minus<LAT>(c, p)));
+        }
+        moments_of<LAT>(gp, gm, drho, jx, jy, jz);
+        const double rho = rho0 + drho;
+        if (rho_out) rho_out[c.own] = rho;
+        if (s_out) {
+            s_out[c.own] = jx / rho;
+            s_out[(size_t)g.n + c.own] = jy / rho;
+            if (L::D == 3) s_out[2 * (size_t)g.n + c.own] = jz / rho;
+        }
+    }
+    red[0][tid] = drho;
+    red[1][tid] = jx;
+    red[2][tid] = jy;
+    red[3][tid] = jz;
+    __syncthreads();
+    for (int h = kRedThreads / 2; h > 0; h >>= 1) {
+        if (tid < h)
+            for (int m = 0; m < 4; ++m) red[m][tid] += red[m][tid + h];
+        __syncthreads();
+    }
+    if (tid < 4) {
+        const uint32_t b = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        partials[4 * (size_t)b + tid] = red[tid][0];
+    }
+}
+
+__global__ __launch_bounds__(kRedThreads) void k_reduce_partials(const double *__restrict__ partials, uint32_t nblocks,
+                                                                 double *__restrict__ totals)
+{
+    __shared__ double red[4][kRedThreads];
+    const int tid = threadIdx.x;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (uint32_t b = tid; b < nblocks; b += kRedThreads)
+        for (int m = 0; m < 4; ++m) acc[m] += partials[4 * (size_t)b + m];
+    for (int m = 0; m < 4; ++m) red[m][tid] = acc[m];
+    __syncthreads();
+    for (int h = kRedThreads / 2; h > 0; h >>= 1) {
+        if (tid < h)
+            for (int m = 0; m < 4; ++m) red[m][tid] += red[m][tid + h];
+        __syncthreads();
+    }
+    if (tid < 4) totals[tid] = red[tid][0];
+}
+
+// Canonical-order permutations of the state (see the file header).
+template <int LAT, typename S, int MODE>
+__global__ __launch_bounds__(256) void k_permute(const void *__restrict__ in, void *__restrict__ out, const Grid g,
+                                                 const StepConsts<double> k)
+{
+    using L = Lattice<LAT>;
+    constexpr int NP = L::NP;
+    const int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int32_t z = blockIdx.z;
+    if (x >= g.nx || y >= g.ny) return;
+    const Cell c = cell_of(g, x, y, z);
+    auto move = [&](int i, uint32_t state_idx, double sigma) {
+        if constexpr (MODE == 0) {
+            st_at(plane((S *)out, i, g.n), c.own, ld_at(plane((const S *)in, i, g.n), state_idx));
+        } else if constexpr (MODE == 1) {
+            st_at(plane((S *)out, i, g.n), state_idx, ld_at(plane((const S *)in, i, g.n), c.own));
+        } else {
+            const double v = (double)Conv<S>::ld(ld_at(plane((const S *)in, i, g.n), state_idx));
+            st_at(plane((double *)out, i, g.n), c.own, v + sigma);
+        }
+    };
+    move(0, c.own, k.sigma[0]);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        move(2 * p + 1, src_plus<LAT>(c, p), k.sigma[p + 1]);
+        move(2 * p + 2, src_minus<LAT>(c, p), k.sigma[p + 1]);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst, uint64_t n)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+// ---- dispatch helpers ------------------------------------------------------------------------
+
+template <typename F> hipError_t by_lattice(int lattice, F &&f)
+{
+    switch (lattice) {
+    case kD2Q9: return f(std::integral_constant<int, kD2Q9>{});
+    case kD3Q19: return f(std::integral_constant<int, kD3Q19>{});
+    case kD3Q27: return f(std::integral_constant<int, kD3Q27>{});
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename F> hipError_t by_storage(int storage, F &&f)
+{
+    switch (storage) {
+    case kF64: return f(double{});
+    case kF32: return f(float{});
+    case kF16: return f(_Float16{});
+    case kBF16: return f(bf16_t{});
+    default: return hipErrorInvalidValue;
+    }
+}
+
+dim3 cell_grid(const Grid &g, int bx, int by)
+{
+    return dim3((uint32_t)((g.nx + bx - 1) / bx), (uint32_t)((g.ny + by - 1) / by), (uint32_t)g.nz);
+}
+
+constexpr int kBlockX = 64;
+constexpr int kBlockY = 4;
+
+}  // namespace
+
+hipError_t launch_init(int lattice, int storage, int order, const Grid &g, const StepConsts<double> &k,
+                       const double *rho, const double *s, void *dst, hipStream_t stream)
+{
+    return by_lattice(lattice, [&](auto lat) {
+        return by_storage(storage, [&](auto sv) {
+            using S = decltype(sv);
+            constexpr int LAT = decltype(lat)::value;
+            const dim3 grid = cell_grid(g, kBlockX, kBlockY), block(kBlockX, kBlockY);
+            if (order == 2)
+                hipLaunchKernelGGL((k_init<LAT, S, 2>), grid, block, 0, stream, rho, s, (S *)dst, g, k);
+            else
+                hipLaunchKernelGGL((k_init<LAT, S, 3>), grid, block, 0, stream, rho, s, (S *)dst, g, k);
+            return hipGetLastError();
+        });
+    });
+}
+
+hipError_t launch_step(int lattice, int storage, int order, const Grid &g, const StepConsts<double> &k64,
+                       const StepConsts<float> &k32, const void *src, void *dst, int block_x, int block_y,
+                       hipStream_t stream)
+{
+    return by_lattice(lattice, [&](auto lat) {
+        return by_storage(storage, [&](auto sv) {
+            using S = decltype(sv);
+            using C = typename Conv<S>::C;
+            constexpr int LAT = decltype(lat)::value;
+            const StepConsts<C> *kc;
+            if constexpr (sizeof(C) == 8) kc = &k64; else kc = &k32;
+            const dim3 grid = cell_grid(g, block_x, block_y), block(block_x, block_y);
+            if (order == 2)
+                hipLaunchKernelGGL((k_step<LAT, S, 2>), grid, block, 0, stream, (const S *)src, (S *)dst, g, *kc);
+            else
+                hipLaunchKernelGGL((k_step<LAT, S, 3>), grid, block, 0, stream, (const S *)src, (S *)dst, g, *kc);
+            return hipGetLastError();
+        });
+    });
+}
+
+uint32_t moments_blocks(const Grid &g)
+{
+    const dim3 grid = cell_grid(g, kBlockX, kRedThreads / kBlockX);
+    return grid.x * grid.y * grid.z;
+}
+
+hipError_t launch_moments(int lattice, int storage, const Grid &g, const StepConsts<double> &k, const void *src,
+                          double *rho, double *s, double *partials, double *totals, hipStream_t stream)
+{
+    return by_lattice(lattice, [&](auto lat) {
+        return by_storage(storage, [&](auto sv) {
+            using S = decltype(sv);
+            constexpr int LAT = decltype(lat)::value;
+            const dim3 grid = cell_grid(g, kBlockX, kRedThreads / kBlockX), block(kBlockX, kRedThreads / kBlockX);
+            hipLaunchKernelGGL((k_moments<LAT, S>), grid, block, 0, stream, (const S *)src, rho, s, partials, g,
+                               k.rho0);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kRedThreads), 0, stream, partials,
+                               grid.x * grid.y * grid.z, totals);
+            return hipGetLastError();
+        });
+    });
+}
+
+hipError_t launch_permute(int lattice, int storage, int mode, const Grid &g, const StepConsts<double> &k,
+                          const void *src, void *dst, hipStream_t stream)
+{
+    return by_lattice(lattice, [&](auto lat) {
+        return by_storage(storage, [&](auto sv) {
+            using S = decltype(sv);
+            constexpr int LAT = decltype(lat)::value;
+            const dim3 grid = cell_grid(g, kBlockX, kBlockY), block(kBlockX, kBlockY);
+            if (mode == 0)
+                hipLaunchKernelGGL((k_permute<LAT, S, 0>), grid, block, 0, stream, src, dst, g, k);
+            else if (mode == 1)
+                hipLaunchKernelGGL((k_permute<LAT, S, 1>), grid, block, 0, stream, src, dst, g, k);
+            else
+                hipLaunchKernelGGL((k_permute<LAT, S, 2>), grid, block, 0, stream, src, dst, g, k);
+            return hipGetLastError();
+        });
+    });
+}
+
+hipError_t launch_copy(void *dst, const void *src, int64_t nbytes, hipStream_t stream)
+{
+    const uint64_t n = (uint64_t)nbytes / 16;
+    if (n == 0) return hipSuccess;
+    const uint64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_copy, dim3((uint32_t)blocks), dim3(256), 0, stream, (const uint4 *)src, (uint4 *)dst, n);
+    return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,0 +1,261 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle on the same seeded
+inputs, element by element. Errors are relative to the oracle's maxima, velocity errors
+relative to the initial velocity amplitude u0:
+
+    e(f) = max|f - f_or| / max|f_or|,  e(rho) = max|rho - rho_or| / max|rho_or|,
+    e(s) = max|s - s_or| / u0.
+
+Gates: 1e-12 for FP64 storage, 1e-5 for FP32 storage (both on all three fields).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+lbm = pytest.importorskip("paper_2605_27004_amd")
+
+TOL = {"f64": 1e-12, "f32": 1e-5}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _perm(name):
+    """perm[i] = oracle index of the library's canonical direction i."""
+    _, _, c, _, _ = lbm.lbm_lattice_info(lbm.LATTICES[name])
+    oc, _, _ = oracle.lattice(name)
+    idx = {tuple(v): i for i, v in enumerate(oc.tolist())}
+    return np.array([idx[tuple(v)] for v in c])
+
+
+def gpu_run(wl, storage, steps, order=None, shift="rest", block=None, chunks=1):
+    order = wl.order if order is None else order
+    p = lbm.make_params(wl.lattice, storage, wl.shape, wl.tensor, wl.tensor_kind, wl.tau, order, shift=shift)
+    sim = lbm.Simulation(p, wl.rho, wl.s)
+    if block:
+        sim.set_launch(*block)
+    left = steps
+    for _ in range(chunks):
+        k = left // chunks if chunks > 1 else left
+        sim.step(k)
+        left -= k
+    sim.step(left)
+    rho, s, tot = sim.moments()
+    f = sim.f64()
+    torch.cuda.synchronize()
+    out = dict(f=f.cpu().numpy(), rho=rho.cpu().numpy(), s=s.cpu().numpy(), totals=tot, t=sim.t, sim=sim)
+    return out
+
+
+def oracle_run(wl, steps, order=None):
+    order = wl.order if order is None else order
+    f, rho, s = oracle.run(wl.lattice, wl.shape, wl.tensor, wl.tensor_kind, wl.tau, wl.rho, wl.s, steps, order)
+    return dict(f=f[_perm(wl.lattice)], rho=rho, s=s)
+
+
+def errors(g, o, u0):
+    return dict(f=np.abs(g["f"] - o["f"]).max() / np.abs(o["f"]).max(),
+                rho=np.abs(g["rho"] - o["rho"]).max() / np.abs(o["rho"]).max(),
+                s=np.abs(g["s"] - o["s"]).max() / u0)
+
+
+def check(wl, storage, steps, order=None, **kw):
+    print(f"[parity] {wl.lattice} {wl.shape} {storage} order={order or wl.order} steps={steps}", flush=True)
+    g = gpu_run(wl, storage, steps, order, **kw)
+    o = oracle_run(wl, steps, order)
+    e = errors(g, o, wl.u0)
+    print(f"[parity] errors {e}", flush=True)
+    assert g["t"] == steps
+    for k, v in e.items():
+        assert v <= TOL[storage], (k, v)
+    return g, o, e
+
+
+def _random_wl(lattice, shape, seed, tau=0.75, order=3):
+    d = W.DIMS[lattice]
+    rho, s = W.random_fields(shape, d, seed)
+    t = W.config1_theta() if d == 2 else W.random_theta(seed)
+    return W.Workload(lattice, shape, t, "theta", tau, 0, rho, s, 0.02, order=order)
+
+
+# ---- FP64: 1e-12 -----------------------------------------------------------------------------
+
+def test_config1_d2q9_fp64_full():
+    """The paper-sized D2Q9 64 x 64 case, 1000 steps."""
+    wl = W.config1()
+    check(wl, "f64", wl.steps)
+
+
+@pytest.mark.parametrize("order", [2, 3])
+@pytest.mark.parametrize("lattice,shape", [("D2Q9", (37, 23, 1)), ("D3Q19", (19, 13, 11)),
+                                           ("D3Q27", (13, 11, 7)), ("D3Q19", (70, 5, 3))])
+def test_ragged_fp64(lattice, shape, order):
+    """Grids that are not multiples of the 64 x 4 work-group tile, random fields."""
+    wl = _random_wl(lattice, shape, seed=5, order=order)
+    check(wl, "f64", 60)
+
+
+@pytest.mark.parametrize("lattice,shape", [("D2Q9", (1, 1, 1)), ("D3Q19", (1, 1, 1)), ("D3Q27", (1, 1, 1)),
+                                           ("D3Q27", (1, 1, 9)), ("D3Q19", (1, 7, 1)), ("D2Q9", (65, 1, 1)),
+                                           ("D3Q19", (2, 2, 2))])
+def test_degenerate_grids_fp64(lattice, shape):
+    """Extents of 1 and 2 make every neighbour wrap onto the cell itself or its twin."""
+    wl = _random_wl(lattice, shape, seed=6)
+    check(wl, "f64", 25)
+
+
+@pytest.mark.parametrize("kind", ["A", "Atilde"])
+def test_tensor_kinds_fp64(kind):
+    rng = np.random.default_rng(3)
+    g = rng.normal(size=(3, 3))
+    q, _ = np.linalg.qr(g)
+    a = q @ np.diag(rng.uniform(0.7, 1.3, 3)) @ q.T
+    wl = _random_wl("D3Q27", (9, 8, 7), seed=8)
+    wl.tensor, wl.tensor_kind = a, kind
+    check(wl, "f64", 30)
+
+
+def test_e1_taylor_green_fp64():
+    """Sec. 4's experiment, A~_xy = 0.4, 400 steps, third order."""
+    wl = W.e1_taylor_green(0.4, 3)
+    check(wl, "f64", wl.steps)
+
+
+# ---- FP32: 1e-5 -------------------------------------------------------------------------------
+
+def test_config1_d2q9_fp32_full():
+    wl = W.config1()
+    check(wl, "f32", wl.steps)
+
+
+def test_config2_d3q19_fp32_reduced_full_steps():
+    """The headline workload's generator (seeded tensor, tau = 0.7, 3-D Taylor-Green u0 = 0.02)
+    at 48^3 for the full 1000 steps."""
+    wl = W.config2(n=48)
+    check(wl, "f32", wl.steps)
+
+
+@pytest.mark.parametrize("lattice,shape,steps", [("D3Q19", (37, 29, 23), 300), ("D3Q27", (33, 17, 21), 300),
+                                                 ("D2Q9", (131, 67, 1), 500)])
+def test_ragged_fp32_taylor_green(lattice, shape, steps):
+    if lattice == "D2Q9":
+        rho, s = _tg2(shape)
+        wl = W.Workload("D2Q9", shape, W.config1_theta(), "theta", 0.8, steps, rho, s, 0.02)
+    else:
+        wl = W.config2(lattice=lattice, shape=shape)
+    check(wl, "f32", steps)
+
+
+def _tg2(shape):
+    x, y, _ = W.grid(shape)
+    kx, ky = 2 * np.pi / shape[0], 2 * np.pi / shape[1]
+    return np.ones(x.size), np.stack([-0.02 * np.cos(kx * x) * np.sin(ky * y), 0.02 * np.sin(kx * x) * np.cos(ky * y)])
+
+
+def test_config2_full_size_fp32():
+    """D3Q19 256^3 in the benchmark's launch configuration: element-wise parity against the
+    oracle after 4 steps (the oracle's whole-grid budget), then conservation of mass and
+    momentum over the workload's 1000 steps on the GPU alone."""
+    wl = W.config2(n=256)
+    g, _, _ = check(wl, "f32", 4)
+    sim = g["sim"]
+    tot0 = g["totals"]
+    sim.step(wl.steps - 4)
+    _, _, tot = sim.moments(fields=False)
+    assert sim.t == wl.steps
+    assert abs(tot[0] - tot0[0]) / tot0[0] < 1e-9
+    cells = wl.cells
+    assert max(abs(tot[a] - tot0[a]) for a in (1, 2, 3)) / (cells * wl.u0) < 1e-7
+
+
+# ---- properties of the library's own machinery --------------------------------------------------
+
+def test_launch_shape_does_not_change_results():
+    wl = W.config2(lattice="D3Q19", shape=(150, 21, 9))
+    ref = gpu_run(wl, "f32", 20)["f"]
+    for block in [(128, 2), (256, 1), (64, 1), (192, 1)]:
+        got = gpu_run(wl, "f32", 20, block=block)["f"]
+        assert np.array_equal(ref, got), block
+
+
+def test_checkpoint_restore_is_exact():
+    wl = W.config2(lattice="D3Q27", shape=(24, 20, 18))
+    p = lbm.make_params(wl.lattice, "f32", wl.shape, wl.tensor, wl.tensor_kind, wl.tau)
+    a = lbm.Simulation(p, wl.rho, wl.s)
+    a.step(13)
+    snap = a.get_populations()
+    a.step(17)
+    fa = a.f64().cpu().numpy()
+    b = lbm.Simulation(p, np.ones(wl.cells), np.zeros((3, wl.cells)))
+    b.set_populations(snap)
+    assert torch.equal(b.get_populations(), snap)
+    b.step(17)
+    assert np.array_equal(b.f64().cpu().numpy(), fa)
+
+
+def test_moments_match_oracle_moments_of_same_state():
+    wl = _random_wl("D3Q19", (17, 9, 5), seed=12)
+    g = gpu_run(wl, "f64", 11)
+    rho, s = oracle.moments("D3Q19", np.ascontiguousarray(g["f"][np.argsort(_perm("D3Q19"))]))
+    assert np.abs(g["rho"] - rho).max() < 1e-15
+    assert np.abs(g["s"] - s).max() < 1e-16
+    assert g["totals"][0] == pytest.approx(rho.sum(), rel=1e-14)
+
+
+def test_totals_are_bit_reproducible():
+    wl = W.config2(n=40)
+    g = gpu_run(wl, "f32", 7)
+    sim = g["sim"]
+    a = sim.moments(fields=False)[2]
+    b = sim.moments(fields=False)[2]
+    assert a == b
+
+
+def test_weight_shift_fp32_matches_oracle():
+    wl = W.config2(n=32)
+    check(wl, "f32", 200, shift="weight")
+
+
+def test_nonfinite_state_is_reported():
+    wl = _random_wl("D2Q9", (8, 8, 1), seed=2)
+    wl.rho = wl.rho.copy()
+    wl.rho[5] = np.nan
+    p = lbm.make_params(wl.lattice, "f64", wl.shape, wl.tensor, wl.tensor_kind, wl.tau)
+    sim = lbm.Simulation(p, wl.rho, wl.s)
+    sim.step(2)
+    with pytest.raises(lbm.LBMError) as ei:
+        sim.moments(fields=False)
+    assert ei.value.code == lbm.LBM_ERR_NONFINITE
+
+
+def test_stream_copy_kernel():
+    a = torch.arange(1 << 20, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    lbm.lbm_stream_copy(b, a, a.numel() * 4, torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+# ---- reduced-precision storage (FP32 arithmetic): error against FP64, stated per field ----------
+
+@pytest.mark.parametrize("storage,shift,bounds", [
+    ("f16", "rest", dict(f=2e-4, rho=1e-4, s=5e-2)),
+    ("bf16", "rest", dict(f=1e-2, rho=1e-3, s=1.0)),
+])
+def test_half_storage_error_is_bounded(storage, shift, bounds):
+    """Half-width storage of the shifted deviations: not a parity claim, a measured error
+    budget (config 1 at 1000 steps)."""
+    wl = W.config1()
+    g = gpu_run(wl, storage, wl.steps, shift=shift)
+    o = oracle_run(wl, wl.steps)
+    e = errors(g, o, wl.u0)
+    print(f"[half] {storage} {shift} {e}", flush=True)
+    for k in bounds:
+        assert e[k] <= bounds[k], (k, e[k])
