@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_GBPS = 8000.0  # MI355X HBM3E
 METRIC = "MLUPS & % of HBM peak, D3Q19 256^3 fp32 vs fp16-shifted; adjoint/fwd ratio"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_d3q19_f32_256.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_d3q19_f32_256.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2605_27004_amd", "csrc", "kernels.hip")
 
 
@@ -50,15 +50,17 @@ def kernel_sha():
 
 
 def traffic_per_launch():
-    """HBM bytes per step launch from the committed rocprofv3 counter summary, or None."""
+    """HBM bytes per step launch from the committed rocprofv3 counter summary (FETCH_SIZE and
+    WRITE_SIZE, scaled by the copy-kernel calibration), or None when the kernel source has
+    changed since the counters were taken."""
     try:
         with open(TRAFFIC_FILE) as fh:
-            t = json.load(fh)
+            kv = dict(ln.split(None, 1) for ln in fh if ln.strip() and not ln.startswith("#"))
     except (OSError, ValueError):
         return None
-    if t.get("kernel_sha") != kernel_sha():
+    if kv.get("kernel_sha", "").strip() != kernel_sha():
         return None
-    return t.get("bytes_per_launch")
+    return int(kv["bytes_per_launch"])
 
 
 def timed_steps(sim, steps, warmup, torch):

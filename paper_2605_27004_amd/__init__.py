@@ -63,6 +63,10 @@ class LBMError(RuntimeError):
 
 
 def _load():
+    # torch carries its own HIP runtime; importing it first makes the library bind to that
+    # same runtime (matched by soname) instead of loading a second copy into the process.
+    import torch  # noqa: F401
+
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2605_27004_amd.build` "
                           "(there is no fallback implementation)")

@@ -7,6 +7,9 @@ relative to the initial velocity amplitude u0:
 
 Gates: 1e-12 for FP64 storage, 1e-5 for FP32 storage (both on all three fields).
 """
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -72,10 +75,20 @@ def check(wl, storage, steps, order=None, **kw):
     o = oracle_run(wl, steps, order)
     e = errors(g, o, wl.u0)
     print(f"[parity] errors {e}", flush=True)
+    _log(dict(lattice=wl.lattice, shape=list(wl.shape), storage=storage, order=order or wl.order, steps=steps,
+              shift=kw.get("shift", "rest"), reference="oracle", **{k: float(v) for k, v in e.items()}))
     assert g["t"] == steps
     for k, v in e.items():
         assert v <= TOL[storage], (k, v)
     return g, o, e
+
+
+def _log(rec):
+    """Append one error record to $PARITY_LOG (JSON lines) when it is set."""
+    path = os.environ.get("PARITY_LOG")
+    if path:
+        with open(path, "a") as fh:
+            fh.write(json.dumps(rec) + "\n")
 
 
 def _random_wl(lattice, shape, seed, tau=0.75, order=3):
@@ -162,7 +175,10 @@ def _tg2(shape):
 def test_config2_full_size_fp32():
     """D3Q19 256^3 in the benchmark's launch configuration: element-wise parity against the
     oracle after 4 steps (the oracle's whole-grid budget), then conservation of mass and
-    momentum over the workload's 1000 steps on the GPU alone."""
+    momentum over the workload's 1000 steps on the GPU alone. FP32 round-off of the stored
+    deviations (|g| ~ 1e-2, half-ulp 6e-10) is unbiased after the moment closure, so the
+    drift is a random walk far below the gates (mass 1e-9 of the total, momentum 1e-7 of
+    N u0)."""
     wl = W.config2(n=256)
     g, _, _ = check(wl, "f32", 4)
     sim = g["sim"]
@@ -170,9 +186,28 @@ def test_config2_full_size_fp32():
     sim.step(wl.steps - 4)
     _, _, tot = sim.moments(fields=False)
     assert sim.t == wl.steps
-    assert abs(tot[0] - tot0[0]) / tot0[0] < 1e-9
-    cells = wl.cells
-    assert max(abs(tot[a] - tot0[a]) for a in (1, 2, 3)) / (cells * wl.u0) < 1e-7
+    drift_m = abs(tot[0] - tot0[0]) / tot0[0]
+    drift_j = max(abs(tot[a] - tot0[a]) for a in (1, 2, 3)) / (wl.cells * wl.u0)
+    _log(dict(case="config2_full_conservation", mass_drift=drift_m, momentum_drift=drift_j, steps=wl.steps))
+    assert drift_m < 1e-9
+    assert drift_j < 1e-7
+
+
+def test_config2_full_size_fp32_vs_fp64_path():
+    """The full 1000-step headline workload at 256^3: the FP32 path against the FP64 path of
+    the same library (which matches the oracle to 1e-12 on every size the oracle can run),
+    on every population, density and velocity of the grid."""
+    wl = W.config2(n=256)
+    a = gpu_run(wl, "f32", wl.steps)
+    a.pop("sim")
+    b = gpu_run(wl, "f64", wl.steps)
+    b.pop("sim")
+    e = errors(a, b, wl.u0)
+    print(f"[parity] full-size f32 vs f64 {e}", flush=True)
+    _log(dict(lattice=wl.lattice, shape=list(wl.shape), storage="f32", order=3, steps=wl.steps,
+              reference="f64 path", **{k: float(v) for k, v in e.items()}))
+    for k, v in e.items():
+        assert v <= TOL["f32"], (k, v)
 
 
 # ---- properties of the library's own machinery --------------------------------------------------
@@ -257,5 +292,7 @@ def test_half_storage_error_is_bounded(storage, shift, bounds):
     o = oracle_run(wl, wl.steps)
     e = errors(g, o, wl.u0)
     print(f"[half] {storage} {shift} {e}", flush=True)
+    _log(dict(lattice=wl.lattice, shape=list(wl.shape), storage=storage, order=3, steps=wl.steps, shift=shift,
+              reference="oracle", **{k: float(v) for k, v in e.items()}))
     for k in bounds:
         assert e[k] <= bounds[k], (k, e[k])
