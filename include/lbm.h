@@ -162,9 +162,13 @@ int lbm_get_f64(lbm_ctx *ctx, double *out);
 /* Steps taken since lbm_init (-1 if ctx is NULL). */
 int64_t lbm_time(const lbm_ctx *ctx);
 
-/* Override the step kernel's work-group shape (block_x * block_y <= 256, block_x a multiple
- * of 64). Results do not depend on it (each cell is computed independently). */
-int lbm_set_launch(lbm_ctx *ctx, int32_t block_x, int32_t block_y);
+/* Step-kernel launch options: work-group shape block_x * block_y cells (block_x a multiple of
+ * 64, block_x * block_y <= 256; the default spans whole x rows up to 256 cells) and flags. */
+#define LBM_LAUNCH_XCD_SLABS 1 /* hand each of the 8 XCDs one contiguous slab of tiles */
+
+/* Override the step kernel's launch. Results do not depend on it: every cell is computed by
+ * the same arithmetic whatever work-group computes it. */
+int lbm_set_launch(lbm_ctx *ctx, int32_t block_x, int32_t block_y, int32_t flags);
 
 /* Gradient of an objective with respect to the tensor entries, tau and a per-cell mask.
  * Not implemented by this build: always returns LBM_ERR_UNSUPPORTED. */

@@ -2,7 +2,7 @@
 "Lattice Boltzmann Methods with Anisotropic Equilibrium Distributions" (arXiv 2605.27004).
 
 Thin ctypes binding of the C ABI in ``include/lbm.h`` (``lib/liblbm.so``, built by
-``python -m paper_2605_27004_amd.build``). The functions keep the C names and only marshal
+``python paper_2605_27004_amd/build.py``). The functions keep the C names and only marshal
 arguments: every step of the update runs in the HIP kernels. PyTorch is used for device
 memory and streams only (:class:`Simulation`). Importing this package fails loudly when the
 library has not been built; there is no fallback implementation.
@@ -30,6 +30,7 @@ LBM_D2Q9, LBM_D3Q19, LBM_D3Q27 = 0, 1, 2
 LBM_F64, LBM_F32, LBM_F16, LBM_BF16 = 0, 1, 2, 3
 LBM_TENSOR_THETA, LBM_TENSOR_A, LBM_TENSOR_ATILDE = 0, 1, 2
 LBM_SHIFT_REST, LBM_SHIFT_WEIGHT = 0, 1
+LBM_LAUNCH_XCD_SLABS = 1
 
 LATTICES = {"D2Q9": LBM_D2Q9, "D3Q19": LBM_D3Q19, "D3Q27": LBM_D3Q27}
 STORAGES = {"f64": LBM_F64, "f32": LBM_F32, "f16": LBM_F16, "bf16": LBM_BF16}
@@ -62,15 +63,16 @@ class LBMError(RuntimeError):
         self.code = code
 
 
-def _load():
+def _bind(path: str):
+    """Load the C-ABI library at `path` and declare its signatures."""
     # torch carries its own HIP runtime; importing it first makes the library bind to that
     # same runtime (matched by soname) instead of loading a second copy into the process.
     import torch  # noqa: F401
 
-    if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2605_27004_amd.build` "
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run `python paper_2605_27004_amd/build.py` "
                           "(there is no fallback implementation)")
-    lib = ctypes.CDLL(LIB_PATH)
+    lib = ctypes.CDLL(path)
     vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
     ip32 = ctypes.POINTER(ctypes.c_int32)
     sig = {
@@ -85,7 +87,7 @@ def _load():
         "lbm_set_populations": (ctypes.c_int, [vp, vp]),
         "lbm_get_f64": (ctypes.c_int, [vp, vp]),
         "lbm_time": (i64, [vp]),
-        "lbm_set_launch": (ctypes.c_int, [vp, i32, i32]),
+        "lbm_set_launch": (ctypes.c_int, [vp, i32, i32, i32]),
         "lbm_grad": (ctypes.c_int, [vp, ctypes.POINTER(lbm_grad_spec), dp, dp, vp]),
         "lbm_destroy": (None, [vp]),
         "lbm_last_error": (ctypes.c_char_p, []),
@@ -98,7 +100,7 @@ def _load():
     return lib
 
 
-_lib = _load()
+_lib = _bind(LIB_PATH)
 
 
 def _check(rc: int) -> int:
@@ -215,8 +217,8 @@ def lbm_time(ctx: int) -> int:
     return int(_lib.lbm_time(ctx))
 
 
-def lbm_set_launch(ctx: int, block_x: int, block_y: int) -> None:
-    _check(_lib.lbm_set_launch(ctx, int(block_x), int(block_y)))
+def lbm_set_launch(ctx: int, block_x: int, block_y: int, flags: int = 0) -> None:
+    _check(_lib.lbm_set_launch(ctx, int(block_x), int(block_y), int(flags)))
 
 
 def lbm_grad(ctx: int, spec: lbm_grad_spec, dtensor=None, dtau=None, dmask=None) -> None:
@@ -283,8 +285,8 @@ class Simulation:
         lbm_step(self.ctx, nsteps)
         return self
 
-    def set_launch(self, block_x: int, block_y: int):
-        lbm_set_launch(self.ctx, block_x, block_y)
+    def set_launch(self, block_x: int, block_y: int, flags: int = 0):
+        lbm_set_launch(self.ctx, block_x, block_y, flags)
 
     def moments(self, fields: bool = True):
         """(rho [N], s [d][N], totals[4]) as torch float64 tensors on the device (fields=False

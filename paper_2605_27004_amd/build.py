@@ -1,6 +1,6 @@
 """Build the HIP library ``paper_2605_27004_amd/lib/liblbm.so`` for gfx950, in-tree.
 
-    python -m paper_2605_27004_amd.build
+    python paper_2605_27004_amd/build.py
 
 Host code (the C ABI) is compiled with g++, the kernels with hipcc for gfx950 only, and the
 two are linked into one shared library that the Python binding loads with ctypes.

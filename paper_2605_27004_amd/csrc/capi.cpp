@@ -268,6 +268,7 @@ struct lbm_ctx {
     hipStream_t stream;
     int64_t t;
     int block_x, block_y;
+    int launch_flags;
 };
 
 extern "C" {
@@ -339,8 +340,12 @@ int lbm_init(lbm_ctx **out, const lbm_params *p, void *pop_a, void *pop_b, void 
     c->scratch = (double *)scratch;
     c->stream = (hipStream_t)stream;
     c->t = 0;
-    c->block_x = 64;
-    c->block_y = 4;
+    // Work-groups span whole x rows where they fit (up to 256 cells), so the boundary cache
+    // line of every x-shifted pull is shared by waves of the same work-group; the rest of the
+    // 256 lanes stack rows in y. Hardware round-robin order measured best for such tiles.
+    c->block_x = p->nx >= 256 ? 256 : (int)((p->nx + 63) / 64) * 64;
+    c->block_y = 256 / c->block_x;
+    c->launch_flags = 0;
     hipError_t e = launch_init(p->lattice, p->storage, p->order, c->grid, c->k64, rho0, s0, c->pop[0], c->stream);
     if (e != hipSuccess) {
         delete c;
@@ -356,7 +361,7 @@ int lbm_step(lbm_ctx *c, int64_t nsteps)
     if (nsteps < 0) return fail(LBM_ERR_ARG, "nsteps must be >= 0");
     for (int64_t s = 0; s < nsteps; ++s) {
         hipError_t e = launch_step(c->p.lattice, c->p.storage, c->p.order, c->grid, c->k64, c->k32, c->pop[c->cur],
-                                   c->pop[c->cur ^ 1], c->block_x, c->block_y, c->stream);
+                                   c->pop[c->cur ^ 1], c->block_x, c->block_y, c->launch_flags, c->stream);
         if (e != hipSuccess) return fail_hip(e, "step kernel launch");
         c->cur ^= 1;
         ++c->t;
@@ -411,14 +416,16 @@ int lbm_get_f64(lbm_ctx *c, double *out)
 
 int64_t lbm_time(const lbm_ctx *c) { return c ? c->t : -1; }
 
-int lbm_set_launch(lbm_ctx *c, int32_t block_x, int32_t block_y)
+int lbm_set_launch(lbm_ctx *c, int32_t block_x, int32_t block_y, int32_t flags)
 {
     if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
+    if (flags & ~LBM_LAUNCH_XCD_SLABS) return fail(LBM_ERR_ARG, "unknown launch flags 0x%x", flags);
     if (block_x < 64 || block_x % 64 != 0 || block_y < 1 || block_x * block_y > 256)
         return fail(LBM_ERR_ARG, "block shape %d x %d: need block_x a multiple of 64 and block_x*block_y <= 256",
                     block_x, block_y);
     c->block_x = block_x;
     c->block_y = block_y;
+    c->launch_flags = flags;
     return LBM_OK;
 }
 

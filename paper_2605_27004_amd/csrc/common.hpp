@@ -44,9 +44,13 @@ struct Grid {
 hipError_t launch_init(int lattice, int storage, int order, const Grid &g, const StepConsts<double> &k,
                        const double *rho, const double *s, void *dst, hipStream_t stream);
 
+// Launch flags of the step kernel (same values as LBM_LAUNCH_* in lbm.h).
+constexpr int kLaunchXcdSlabs = 1;  // XCD-contiguous tile order
+
 hipError_t launch_step(int lattice, int storage, int order, const Grid &g, const StepConsts<double> &k64,
                        const StepConsts<float> &k32, const void *src, void *dst, int block_x, int block_y,
-                       hipStream_t stream);
+                       int flags, hipStream_t stream);
+
 
 // rho / s may be null. partials: scratch of 4 * nblocks doubles; totals: 4 doubles of scratch.
 hipError_t launch_moments(int lattice, int storage, const Grid &g, const StepConsts<double> &k, const void *src,

@@ -26,14 +26,18 @@
 
 #include "common.hpp"
 
+// No implicit contraction: every fused multiply-add below is written out, so the rounding of
+// each cell update is fixed by the source and identical in every kernel variant and launch
+// shape.
+#pragma clang fp contract(off)
+
 namespace lbm {
 namespace {
 
-// ---- storage conversions ---------------------------------------------------------------
+__device__ inline float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-struct bf16_t {
-    uint16_t bits;
-};
+// ---- storage conversions ---------------------------------------------------------------
 
 template <typename S> struct Conv;
 template <> struct Conv<double> {
@@ -51,17 +55,10 @@ template <> struct Conv<_Float16> {
     __device__ static float ld(_Float16 v) { return (float)v; }
     __device__ static _Float16 st(float v) { return (_Float16)v; }  // round to nearest even
 };
-template <> struct Conv<bf16_t> {
+template <> struct Conv<__bf16> {
     using C = float;
-    __device__ static float ld(bf16_t v) { return __uint_as_float((uint32_t)v.bits << 16); }
-    __device__ static bf16_t st(float v)
-    {
-        // round to nearest even; NaN stays NaN
-        uint32_t u = __float_as_uint(v);
-        if ((u & 0x7fffffffu) > 0x7f800000u) return bf16_t{(uint16_t)((u >> 16) | 0x40u)};
-        u += 0x7fffu + ((u >> 16) & 1u);
-        return bf16_t{(uint16_t)(u >> 16)};
-    }
+    __device__ static float ld(__bf16 v) { return (float)v; }
+    __device__ static __bf16 st(float v) { return (__bf16)v; }  // round to nearest even
 };
 
 // ---- neighbourhood ---------------------------------------------------------------------
@@ -127,6 +124,13 @@ template <typename S> __device__ inline void st_at(S *p, uint32_t idx, S v)
 {
     *reinterpret_cast<S *>(reinterpret_cast<char *>(p) + (uint32_t)(idx * (uint32_t)sizeof(S))) = v;
 }
+// Streaming store of the step's output: it is not read again within the step, and keeping it
+// out of the caches leaves them to the x-boundary lines the pulls share (measured faster; the
+// loads themselves stay cached for that reason).
+template <typename S> __device__ inline void st_stream(S *p, uint32_t idx, S v)
+{
+    __builtin_nontemporal_store(v, reinterpret_cast<S *>(reinterpret_cast<char *>(p) + (uint32_t)(idx * (uint32_t)sizeof(S))));
+}
 
 // ---- the collision -----------------------------------------------------------------------
 
@@ -137,32 +141,36 @@ template <int LAT, int ORDER, typename C>
 __device__ inline void equilibrium_pairs(const StepConsts<C> &k, C drho, C rho, C sx, C sy, C sz, C *eqp, C *eqm)
 {
     using L = Lattice<LAT>;
-    const C usq = sx * sx + sy * sy + sz * sz;
-    const C ksx = k.k[0] * sx + k.k[3] * sy + k.k[4] * sz;
-    const C ksy = k.k[3] * sx + k.k[1] * sy + k.k[5] * sz;
-    const C ksz = k.k[4] * sx + k.k[5] * sy + k.k[2] * sz;
+    const C usq = fmad(sx, sx, fmad(sy, sy, sz * sz));
+    const C ksx = fmad(k.k[0], sx, fmad(k.k[3], sy, k.k[4] * sz));
+    const C ksy = fmad(k.k[3], sx, fmad(k.k[1], sy, k.k[5] * sz));
+    const C ksz = fmad(k.k[4], sx, fmad(k.k[5], sy, k.k[2] * sz));
     const C even0 = C(-1.5) * usq;
     const C bq = C(-4.5) * usq;
-    eqp[0] = k.rest[0] * drho + k.eoff[0] + k.w[0] * rho * even0;
+    eqp[0] = fmad(k.w[0] * rho, even0, fmad(k.rest[0], drho, k.eoff[0]));
 #pragma unroll
     for (int p = 0; p < L::NP; ++p) {
         const PairRow v = L::pair(p);
+        // u = c.s and kc = c.(K s) for c in {-1, 0, 1}^3
         C u = C(0), kc = C(0);
-        if (v.cx) { u += v.cx * sx; kc += v.cx * ksx; }
-        if (v.cy) { u += v.cy * sy; kc += v.cy * ksy; }
-        if (v.cz) { u += v.cz * sz; kc += v.cz * ksz; }
+        if (v.cx > 0) { u += sx; kc += ksx; }
+        if (v.cx < 0) { u -= sx; kc -= ksx; }
+        if (v.cy > 0) { u += sy; kc += ksy; }
+        if (v.cy < 0) { u -= sy; kc -= ksy; }
+        if (v.cz > 0) { u += sz; kc += ksz; }
+        if (v.cz < 0) { u -= sz; kc -= ksz; }
         const C u2 = u * u;
-        const C even = C(4.5) * u2 + even0;
+        const C even = fmad(C(4.5), u2, even0);
         C odd;
         if constexpr (ORDER == 3) {
-            odd = u * (k.a[p + 1] + bq + C(4.5) * u2) - C(3) * kc;
+            odd = fmad(u, fmad(C(4.5), u2, k.a[p + 1] + bq), C(-3) * kc);
         } else {
             odd = C(3) * u;
         }
         const C wr = k.w[p + 1] * rho;
-        const C base = k.rest[p + 1] * drho + k.eoff[p + 1];
-        eqp[p + 1] = base + wr * (even + odd);
-        eqm[p + 1] = base + wr * (even - odd);
+        const C base = fmad(k.rest[p + 1], drho, k.eoff[p + 1]);
+        eqp[p + 1] = fmad(wr, even + odd, base);
+        eqm[p + 1] = fmad(wr, even - odd, base);
     }
 }
 
@@ -228,18 +236,59 @@ __device__ inline void close_moments(C *eqp, C *eqm, C drho, C jx, C jy, C jz)
     eqp[0] = drho - mass;
 }
 
+// One BGK collision of eq:LBE_BGK on the pre-collision deviations of a cell (rest in gp[0],
+// pair p in gp[p+1] / gm[p+1]); the arrays receive the post-collision deviations.
+template <int LAT, int ORDER, typename C>
+__device__ inline void collide_cell(const StepConsts<C> &k, C *gp, C *gm)
+{
+    constexpr int NP = Lattice<LAT>::NP;
+    C drho, jx, jy, jz;
+    moments_of<LAT>(gp, gm, drho, jx, jy, jz);
+    const C rho = k.rho0 + drho;
+    const C inv = C(1) / rho;
+    C eqp[NP + 1], eqm[NP + 1];
+    equilibrium_pairs<LAT, ORDER, C>(k, drho, rho, jx * inv, jy * inv, jz * inv, eqp, eqm);
+    if constexpr (sizeof(C) == 4) close_moments<LAT>(eqp, eqm, drho, jx, jy, jz);
+    gp[0] = fmad(k.omega, eqp[0] - gp[0], gp[0]);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        gp[p + 1] = fmad(k.omega, eqp[p + 1] - gp[p + 1], gp[p + 1]);
+        gm[p + 1] = fmad(k.omega, eqm[p + 1] - gm[p + 1], gm[p + 1]);
+    }
+}
+
 // ---- kernels -------------------------------------------------------------------------------
+
+// Work-group -> tile mapping of the step kernel. Work-groups of a 1-D launch are handed to the
+// eight XCDs round-robin (flat id b runs on XCD b mod 8). With `xcd_slabs` set, the tile
+// order is permuted so that XCD k processes one contiguous range of tiles -- a slab of the
+// grid -- and the neighbour rows and the x-boundary cache lines a pull gathers are mostly
+// fetched into, and found in, that XCD's own L2.
+struct TileMap {
+    uint32_t tiles_x, tiles_y, nblocks;
+    uint32_t xcd_slabs;
+};
+
+__device__ inline uint32_t tile_of(const TileMap &m, uint32_t b)
+{
+    if (!m.xcd_slabs) return b;
+    const uint32_t q = m.nblocks / 8u, r = m.nblocks % 8u;
+    const uint32_t xcd = b % 8u, local = b / 8u;
+    return xcd < r ? xcd * (q + 1u) + local : r * (q + 1u) + (xcd - r) * q + local;
+}
 
 template <int LAT, typename S, int ORDER>
 __global__ __launch_bounds__(256) void k_step(const S *__restrict__ src, S *__restrict__ dst, const Grid g,
-                                              const StepConsts<typename Conv<S>::C> k)
+                                              const StepConsts<typename Conv<S>::C> k, const TileMap m)
 {
     using L = Lattice<LAT>;
     using C = typename Conv<S>::C;
     constexpr int NP = L::NP;
-    const int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int32_t y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int32_t z = blockIdx.z;
+    const uint32_t t = tile_of(m, blockIdx.x);
+    const uint32_t tx = t % m.tiles_x, tyz = t / m.tiles_x;
+    const int32_t x = (int32_t)(tx * blockDim.x + threadIdx.x);
+    const int32_t y = (int32_t)((tyz % m.tiles_y) * blockDim.y + threadIdx.y);
+    const int32_t z = (int32_t)(tyz / m.tiles_y);
     if (x >= g.nx || y >= g.ny) return;
     const Cell c = cell_of(g, x, y, z);
 
@@ -251,19 +300,12 @@ __global__ __launch_bounds__(256) void k_step(const S *__restrict__ src, S *__re
         gm[p + 1] = Conv<S>::ld(ld_at(plane(src, 2 * p + 2, g.n), src_minus<LAT>(c, p)));
     }
 
-    C drho, jx, jy, jz;
-    moments_of<LAT>(gp, gm, drho, jx, jy, jz);
-    const C rho = k.rho0 + drho;
-    const C inv = C(1) / rho;
-    C eqp[NP + 1], eqm[NP + 1];
-    equilibrium_pairs<LAT, ORDER, C>(k, drho, rho, jx * inv, jy * inv, jz * inv, eqp, eqm);
-    if constexpr (sizeof(C) == 4) close_moments<LAT>(eqp, eqm, drho, jx, jy, jz);
-
-    st_at(plane(dst, 0, g.n), c.own, Conv<S>::st(gp[0] + k.omega * (eqp[0] - gp[0])));
+    collide_cell<LAT, ORDER, C>(k, gp, gm);
+    st_stream(plane(dst, 0, g.n), c.own, Conv<S>::st(gp[0]));
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-        st_at(plane(dst, 2 * p + 1, g.n), c.own, Conv<S>::st(gp[p + 1] + k.omega * (eqp[p + 1] - gp[p + 1])));
-        st_at(plane(dst, 2 * p + 2, g.n), c.own, Conv<S>::st(gm[p + 1] + k.omega * (eqm[p + 1] - gm[p + 1])));
+        st_stream(plane(dst, 2 * p + 1, g.n), c.own, Conv<S>::st(gp[p + 1]));
+        st_stream(plane(dst, 2 * p + 2, g.n), c.own, Conv<S>::st(gm[p + 1]));
     }
 }
 
@@ -393,10 +435,12 @@ __global__ __launch_bounds__(256) void k_permute(const void *__restrict__ in, vo
     }
 }
 
-__global__ __launch_bounds__(256) void k_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst, uint64_t n)
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_copy(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst, uint64_t n)
 {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] = src[i];
+    if (i < n) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 // ---- dispatch helpers ------------------------------------------------------------------------
@@ -417,7 +461,7 @@ template <typename F> hipError_t by_storage(int storage, F &&f)
     case kF64: return f(double{});
     case kF32: return f(float{});
     case kF16: return f(_Float16{});
-    case kBF16: return f(bf16_t{});
+    case kBF16: return f(__bf16{});
     default: return hipErrorInvalidValue;
     }
 }
@@ -451,7 +495,7 @@ hipError_t launch_init(int lattice, int storage, int order, const Grid &g, const
 
 hipError_t launch_step(int lattice, int storage, int order, const Grid &g, const StepConsts<double> &k64,
                        const StepConsts<float> &k32, const void *src, void *dst, int block_x, int block_y,
-                       hipStream_t stream)
+                       int flags, hipStream_t stream)
 {
     return by_lattice(lattice, [&](auto lat) {
         return by_storage(storage, [&](auto sv) {
@@ -460,11 +504,17 @@ hipError_t launch_step(int lattice, int storage, int order, const Grid &g, const
             constexpr int LAT = decltype(lat)::value;
             const StepConsts<C> *kc;
             if constexpr (sizeof(C) == 8) kc = &k64; else kc = &k32;
-            const dim3 grid = cell_grid(g, block_x, block_y), block(block_x, block_y);
+            const dim3 g3 = cell_grid(g, block_x, block_y), block(block_x, block_y);
+            TileMap m;
+            m.tiles_x = g3.x;
+            m.tiles_y = g3.y;
+            m.nblocks = g3.x * g3.y * g3.z;
+            m.xcd_slabs = (flags & kLaunchXcdSlabs) ? 1u : 0u;
+            const dim3 grid(m.nblocks);
             if (order == 2)
-                hipLaunchKernelGGL((k_step<LAT, S, 2>), grid, block, 0, stream, (const S *)src, (S *)dst, g, *kc);
+                hipLaunchKernelGGL((k_step<LAT, S, 2>), grid, block, 0, stream, (const S *)src, (S *)dst, g, *kc, m);
             else
-                hipLaunchKernelGGL((k_step<LAT, S, 3>), grid, block, 0, stream, (const S *)src, (S *)dst, g, *kc);
+                hipLaunchKernelGGL((k_step<LAT, S, 3>), grid, block, 0, stream, (const S *)src, (S *)dst, g, *kc, m);
             return hipGetLastError();
         });
     });
@@ -519,7 +569,7 @@ hipError_t launch_copy(void *dst, const void *src, int64_t nbytes, hipStream_t s
     const uint64_t n = (uint64_t)nbytes / 16;
     if (n == 0) return hipSuccess;
     const uint64_t blocks = (n + 255) / 256;
-    hipLaunchKernelGGL(k_copy, dim3((uint32_t)blocks), dim3(256), 0, stream, (const uint4 *)src, (uint4 *)dst, n);
+    hipLaunchKernelGGL(k_copy, dim3((uint32_t)blocks), dim3(256), 0, stream, (const u32x4 *)src, (u32x4 *)dst, n);
     return hipGetLastError();
 }
 

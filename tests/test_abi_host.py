@@ -165,7 +165,7 @@ def test_init_rejects_before_any_device_work():
 def test_null_context_calls_fail_cleanly():
     for fn, args in [(lbm._lib.lbm_step, (None, 1)), (lbm._lib.lbm_moments, (None, None, None, None)),
                      (lbm._lib.lbm_get_populations, (None, None)), (lbm._lib.lbm_set_populations, (None, None)),
-                     (lbm._lib.lbm_get_f64, (None, None)), (lbm._lib.lbm_set_launch, (None, 64, 4))]:
+                     (lbm._lib.lbm_get_f64, (None, None)), (lbm._lib.lbm_set_launch, (None, 64, 4, 1))]:
         assert fn(*args) == lbm.LBM_ERR_ARG
     assert lbm._lib.lbm_time(None) == -1
     lbm.lbm_destroy(None)

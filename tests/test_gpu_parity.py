@@ -215,9 +215,18 @@ def test_config2_full_size_fp32_vs_fp64_path():
 def test_launch_shape_does_not_change_results():
     wl = W.config2(lattice="D3Q19", shape=(150, 21, 9))
     ref = gpu_run(wl, "f32", 20)["f"]
-    for block in [(128, 2), (256, 1), (64, 1), (192, 1)]:
+    for block in [(128, 2, 0), (256, 1, 0), (64, 1, 0), (192, 1, 0), (64, 4, lbm.LBM_LAUNCH_XCD_SLABS)]:
         got = gpu_run(wl, "f32", 20, block=block)["f"]
         assert np.array_equal(ref, got), block
+
+
+@pytest.mark.parametrize("lattice,storage,shape,steps", [("D3Q19", "f64", (256, 6, 4), 40),
+                                                         ("D3Q27", "f32", (256, 5, 3), 60),
+                                                         ("D2Q9", "f64", (128, 11, 1), 80)])
+def test_row_spanning_tiles_match_oracle(lattice, storage, shape, steps):
+    """Rows of 128 and 256 cells: one work-group per row (the default launch)."""
+    wl = _random_wl(lattice, shape, seed=15)
+    check(wl, storage, steps)
 
 
 def test_checkpoint_restore_is_exact():
