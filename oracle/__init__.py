@@ -50,13 +50,18 @@ def _load():
     lib.orc_lattice.argtypes = [ctypes.c_int, _ip, _ip, _ip, _dp, _dp]
     lib.orc_tensor_to_ainv.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp]
     lib.orc_feq.argtypes = [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_double, _dp, _dp]
+    _u8p = ctypes.POINTER(ctypes.c_uint8)
     lib.orc_init.argtypes = [ctypes.c_int, ctypes.c_int, _i64, _i64, _i64, _dp, _dp, _dp, _dp, ctypes.c_int]
+    lib.orc_init_ext.argtypes = [ctypes.c_int, ctypes.c_int, _i64, _i64, _i64, _dp, _dp, _dp, _u8p, _dp, ctypes.c_int]
     lib.orc_steps.argtypes = [ctypes.c_int, ctypes.c_int, _i64, _i64, _i64, _dp, ctypes.c_double, _i64, _dp,
                               ctypes.c_int]
+    lib.orc_steps_ext.argtypes = [ctypes.c_int, ctypes.c_int, _i64, _i64, _i64, _dp, ctypes.c_double, _i64, _dp,
+                                  _u8p, _dp, ctypes.c_int]
     lib.orc_moments.argtypes = [ctypes.c_int, _i64, _dp, _dp, _dp]
+    lib.orc_moments_ext.argtypes = [ctypes.c_int, _i64, _dp, _u8p, _dp, _dp, _dp]
     lib.orc_num_threads.argtypes = []
-    for name in ("orc_gh1d", "orc_lattice", "orc_tensor_to_ainv", "orc_feq", "orc_init", "orc_steps",
-                 "orc_moments", "orc_num_threads"):
+    for name in ("orc_gh1d", "orc_lattice", "orc_tensor_to_ainv", "orc_feq", "orc_init", "orc_init_ext",
+                 "orc_steps", "orc_steps_ext", "orc_moments", "orc_moments_ext", "orc_num_threads"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -65,6 +70,22 @@ def _load():
 def _ptr(a: np.ndarray):
     assert a.dtype == np.float64 and a.flags.c_contiguous
     return a.ctypes.data_as(_dp)
+
+
+def _mask_ptr(mask, n):
+    """uint8 [N] solid mask (1 = solid) or None, as a ctypes pointer plus the array kept alive."""
+    if mask is None:
+        return None, None
+    m = np.ascontiguousarray(np.asarray(mask).reshape(n).astype(np.uint8))
+    return m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), m
+
+
+def _force_ptr(force, d):
+    if force is None:
+        return None, None
+    fv = np.zeros(3)
+    fv[:d] = np.asarray(force, dtype=np.float64)[:d]
+    return _ptr(fv), fv
 
 
 def dim(lattice: str) -> int:
@@ -127,8 +148,8 @@ def _shape3(shape):
     return shape
 
 
-def init(name: str, shape, ainv, rho0, s0, order: int = 3, nthreads: int = 0) -> np.ndarray:
-    """f(0) = f^eq(rho0, s0) on a grid of shape (nx, ny[, nz])."""
+def init(name: str, shape, ainv, rho0, s0, order: int = 3, nthreads: int = 0, mask=None) -> np.ndarray:
+    """f(0) = f^eq(rho0, s0) on a grid of shape (nx, ny[, nz]); zero on solid cells."""
     nx, ny, nz = _shape3(shape)
     d = dim(name)
     n = nx * ny * nz
@@ -137,42 +158,50 @@ def init(name: str, shape, ainv, rho0, s0, order: int = 3, nthreads: int = 0) ->
     r = np.ascontiguousarray(np.asarray(rho0, dtype=np.float64).reshape(n))
     s = np.ascontiguousarray(np.asarray(s0, dtype=np.float64).reshape(d, n))
     f = np.zeros((q, n))
-    if _load().orc_init(LATTICES[name], int(order), nx, ny, nz, _ptr(a), _ptr(r), _ptr(s), _ptr(f), int(nthreads)):
+    mp, _keep = _mask_ptr(mask, n)
+    if _load().orc_init_ext(LATTICES[name], int(order), nx, ny, nz, _ptr(a), _ptr(r), _ptr(s), mp, _ptr(f),
+                            int(nthreads)):
         raise ValueError(name)
     return f
 
 
 def steps(name: str, shape, ainv, tau: float, f: np.ndarray, nsteps: int, order: int = 3,
-          nthreads: int = 0) -> np.ndarray:
-    """Advance pre-collision populations f ([q][N]) by nsteps of eq:LBE_BGK (in place; returned)."""
+          nthreads: int = 0, mask=None, force=None) -> np.ndarray:
+    """Advance pre-collision populations f ([q][N]) by nsteps of eq:LBE_BGK (in place; returned),
+    with optional solid mask (halfway bounce-back) and body force (exact-difference method)."""
     nx, ny, nz = _shape3(shape)
     d = dim(name)
     a = np.ascontiguousarray(np.asarray(ainv, dtype=np.float64)[:d, :d])
     if not (f.dtype == np.float64 and f.flags.c_contiguous):
         raise TypeError("f must be C-contiguous float64")
-    rc = _load().orc_steps(LATTICES[name], int(order), nx, ny, nz, _ptr(a), float(tau), int(nsteps), _ptr(f),
-                           int(nthreads))
+    mp, _keep_m = _mask_ptr(mask, nx * ny * nz)
+    fp, _keep_f = _force_ptr(force, d)
+    rc = _load().orc_steps_ext(LATTICES[name], int(order), nx, ny, nz, _ptr(a), float(tau), int(nsteps), _ptr(f),
+                               mp, fp, int(nthreads))
     if rc:
         raise RuntimeError(f"orc_steps failed ({rc})")
     return f
 
 
-def moments(name: str, f: np.ndarray):
-    """(rho [N], s [d][N]) from populations (eq:a0discrete_f, eq:a1discrete_f)."""
+def moments(name: str, f: np.ndarray, mask=None, force=None):
+    """(rho [N], s [d][N]) from populations (eq:a0discrete_f, eq:a1discrete_f); with a force the
+    velocity is (sum f c + F/2)/rho; solid cells give zeros."""
     d = dim(name)
     n = f.shape[1]
     rho = np.zeros(n)
     s = np.zeros((d, n))
-    _load().orc_moments(LATTICES[name], n, _ptr(np.ascontiguousarray(f)), _ptr(rho), _ptr(s))
+    mp, _keep_m = _mask_ptr(mask, n)
+    fp, _keep_f = _force_ptr(force, d)
+    _load().orc_moments_ext(LATTICES[name], n, _ptr(np.ascontiguousarray(f)), mp, fp, _ptr(rho), _ptr(s))
     return rho, s
 
 
 def run(name: str, shape, tensor, kind: str, tau: float, rho0, s0, nsteps: int, order: int = 3,
-        nthreads: int = 0):
+        nthreads: int = 0, mask=None, force=None):
     """Initialise at equilibrium and run nsteps; returns (f, rho, s) at t = nsteps."""
     d = dim(name)
     ainv = tensor_to_ainv(np.asarray(tensor, dtype=np.float64)[:d, :d], kind, d)
-    f = init(name, shape, ainv, rho0, s0, order, nthreads)
-    steps(name, shape, ainv, tau, f, nsteps, order, nthreads)
-    rho, s = moments(name, f)
+    f = init(name, shape, ainv, rho0, s0, order, nthreads, mask=mask)
+    steps(name, shape, ainv, tau, f, nsteps, order, nthreads, mask=mask, force=force)
+    rho, s = moments(name, f, mask=mask, force=force)
     return f, rho, s

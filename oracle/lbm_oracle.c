@@ -28,6 +28,15 @@
  *
  * Population arrays are structure-of-arrays f[i][z][y][x] (x fastest) in THIS file's own
  * velocity order (the tensor-product enumeration below); callers map orders by velocity vector.
+ *
+ * Extensions beyond the paper (it names walls and forcing only as future work, Sec. 5); the
+ * definitions below are the ones the library implements, written out plainly:
+ *   - solid cells (mask = 1) carry no populations (kept at zero); a population leaving a fluid
+ *     cell x towards a solid cell x + c_i returns to x in the opposite direction at the next
+ *     step (halfway bounce-back): f_opp(i)(t+1, x) = f*_i(t, x);
+ *   - body force F (momentum per cell per step) by the exact-difference method:
+ *     f*_i = f_i + (f^eq_i(rho, s) - f_i)/tau + [f^eq_i(rho, s + F/rho) - f^eq_i(rho, s)],
+ *     with s = sum_i f_i c_i / rho, and the fluid velocity read out as (sum_i f_i c_i + F/2)/rho.
  */
 #include <math.h>
 #include <stdint.h>
@@ -276,8 +285,8 @@ int orc_num_threads(void)
 }
 
 /* f(0, x) = f^eq(rho0(x), s0(x)). rho0 is [N], s0 is [d][N], f is [q][N]. */
-int orc_init(int lattice, int order, int64_t nx, int64_t ny, int64_t nz, const double *Ainv, const double *rho0,
-             const double *s0, double *f, int nthreads)
+int orc_init_ext(int lattice, int order, int64_t nx, int64_t ny, int64_t nz, const double *Ainv, const double *rho0,
+                 const double *s0, const uint8_t *mask, double *f, int nthreads)
 {
     lattice_t L;
     if (build_lattice(lattice, &L)) return -1;
@@ -290,9 +299,15 @@ int orc_init(int lattice, int order, int64_t nx, int64_t ny, int64_t nz, const d
         double s[3] = {0.0, 0.0, 0.0}, feq[QMAX];
         for (int a = 0; a < L.d; ++a) s[a] = s0[a * N + n];
         feq_cell(&L, order, K, rho0[n], s, feq);
-        for (int i = 0; i < L.q; ++i) f[i * N + n] = feq[i];
+        for (int i = 0; i < L.q; ++i) f[i * N + n] = (mask && mask[n]) ? 0.0 : feq[i];
     }
     return 0;
+}
+
+int orc_init(int lattice, int order, int64_t nx, int64_t ny, int64_t nz, const double *Ainv, const double *rho0,
+             const double *s0, double *f, int nthreads)
+{
+    return orc_init_ext(lattice, order, nx, ny, nz, Ainv, rho0, s0, NULL, f, nthreads);
 }
 
 static int64_t wrap(int64_t v, int64_t n)
@@ -302,9 +317,10 @@ static int64_t wrap(int64_t v, int64_t n)
 }
 
 /* nsteps of eq:LBE_BGK on the periodic grid; f ([q][N]) holds the pre-collision state and
- * is advanced in place (a second array is allocated here). */
-int orc_steps(int lattice, int order, int64_t nx, int64_t ny, int64_t nz, const double *Ainv, double tau,
-              int64_t nsteps, double *f, int nthreads)
+ * is advanced in place (a second array is allocated here). mask ([N], 1 = solid) and force
+ * ([d]) may be NULL; see the header for their definitions. */
+int orc_steps_ext(int lattice, int order, int64_t nx, int64_t ny, int64_t nz, const double *Ainv, double tau,
+                  int64_t nsteps, double *f, const uint8_t *mask, const double *force, int nthreads)
 {
     lattice_t L;
     if (build_lattice(lattice, &L)) return -1;
@@ -313,7 +329,18 @@ int orc_steps(int lattice, int order, int64_t nx, int64_t ny, int64_t nz, const 
     k_from_ainv(L.d, Ainv, K);
     const int64_t N = nx * ny * nz;
     const int q = L.q, d = L.d;
-    double *g = (double *)malloc(sizeof(double) * (size_t)q * (size_t)N);
+    int opp[QMAX];
+    for (int i = 0; i < q; ++i)
+        for (int k = 0; k < q; ++k)
+            if (L.c[k][0] == -L.c[i][0] && L.c[k][1] == -L.c[i][1] && L.c[k][2] == -L.c[i][2]) opp[i] = k;
+    double F[3] = {0.0, 0.0, 0.0};
+    int forced = 0;
+    if (force)
+        for (int a = 0; a < d; ++a) {
+            F[a] = force[a];
+            if (F[a] != 0.0) forced = 1;
+        }
+    double *g = (double *)calloc((size_t)q * (size_t)N, sizeof(double));
     if (!g) return -2;
     set_threads(nthreads);
     double *cur = f, *nxt = g;
@@ -323,7 +350,11 @@ int orc_steps(int lattice, int order, int64_t nx, int64_t ny, int64_t nz, const 
             for (int64_t y = 0; y < ny; ++y)
                 for (int64_t x = 0; x < nx; ++x) {
                     const int64_t n = (z * ny + y) * nx + x;
-                    double rho = 0.0, j[3] = {0.0, 0.0, 0.0}, s[3] = {0.0, 0.0, 0.0}, feq[QMAX];
+                    if (mask && mask[n]) {
+                        for (int i = 0; i < q; ++i) nxt[i * N + n] = 0.0;
+                        continue;
+                    }
+                    double rho = 0.0, j[3] = {0.0, 0.0, 0.0}, s[3] = {0.0, 0.0, 0.0}, feq[QMAX], feqf[QMAX];
                     for (int i = 0; i < q; ++i) {
                         double fi = cur[i * N + n];
                         rho += fi;
@@ -331,13 +362,23 @@ int orc_steps(int lattice, int order, int64_t nx, int64_t ny, int64_t nz, const 
                     }
                     for (int a = 0; a < d; ++a) s[a] = j[a] / rho;
                     feq_cell(&L, order, K, rho, s, feq);
+                    if (forced) {
+                        double sf[3] = {0.0, 0.0, 0.0};
+                        for (int a = 0; a < d; ++a) sf[a] = s[a] + F[a] / rho;
+                        feq_cell(&L, order, K, rho, sf, feqf);
+                    }
                     for (int i = 0; i < q; ++i) {
                         double fi = cur[i * N + n];
                         double post = fi + (feq[i] - fi) / tau;
+                        if (forced) post += feqf[i] - feq[i];
                         int64_t xd = wrap(x + L.c[i][0], nx);
                         int64_t yd = wrap(y + L.c[i][1], ny);
                         int64_t zd = wrap(z + L.c[i][2], nz);
-                        nxt[i * N + (zd * ny + yd) * nx + xd] = post;
+                        int64_t nd = (zd * ny + yd) * nx + xd;
+                        if (mask && mask[nd])
+                            nxt[opp[i] * N + n] = post; /* halfway bounce-back */
+                        else
+                            nxt[i * N + nd] = post;
                     }
                 }
         double *tmp = cur;
@@ -349,13 +390,26 @@ int orc_steps(int lattice, int order, int64_t nx, int64_t ny, int64_t nz, const 
     return 0;
 }
 
-/* rho = sum_i f_i, s = sum_i f_i c_i / rho. rho is [N], s is [d][N]. */
-int orc_moments(int lattice, int64_t N, const double *f, double *rho, double *s)
+int orc_steps(int lattice, int order, int64_t nx, int64_t ny, int64_t nz, const double *Ainv, double tau,
+              int64_t nsteps, double *f, int nthreads)
+{
+    return orc_steps_ext(lattice, order, nx, ny, nz, Ainv, tau, nsteps, f, NULL, NULL, nthreads);
+}
+
+/* rho = sum_i f_i, s = (sum_i f_i c_i + F/2) / rho (F = 0 when force is NULL); solid cells
+ * (mask = 1) give rho = 0 and s = 0. rho is [N], s is [d][N]. */
+int orc_moments_ext(int lattice, int64_t N, const double *f, const uint8_t *mask, const double *force, double *rho,
+                    double *s)
 {
     lattice_t L;
     if (build_lattice(lattice, &L)) return -1;
 #pragma omp parallel for schedule(static)
     for (int64_t n = 0; n < N; ++n) {
+        if (mask && mask[n]) {
+            rho[n] = 0.0;
+            for (int a = 0; a < L.d; ++a) s[a * N + n] = 0.0;
+            continue;
+        }
         double r = 0.0, j[3] = {0.0, 0.0, 0.0};
         for (int i = 0; i < L.q; ++i) {
             double fi = f[i * N + n];
@@ -363,7 +417,12 @@ int orc_moments(int lattice, int64_t N, const double *f, double *rho, double *s)
             for (int a = 0; a < L.d; ++a) j[a] += fi * L.c[i][a];
         }
         rho[n] = r;
-        for (int a = 0; a < L.d; ++a) s[a * N + n] = j[a] / r;
+        for (int a = 0; a < L.d; ++a) s[a * N + n] = (j[a] + (force ? 0.5 * force[a] : 0.0)) / r;
     }
     return 0;
+}
+
+int orc_moments(int lattice, int64_t N, const double *f, double *rho, double *s)
+{
+    return orc_moments_ext(lattice, N, f, NULL, NULL, rho, s);
 }

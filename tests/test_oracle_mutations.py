@@ -26,6 +26,9 @@ MUTANTS = {
     "d3q19_weights": ("(n2 == 1) ? 1.0 / 18.0 : 1.0 / 36.0", "(n2 == 1) ? 1.0 / 12.0 : 1.0 / 48.0"),
     "atilde_sqrt_always": ("double scale = pow(det, 1.0 / d);", "double scale = sqrt(det);"),
     "y_index_swap": ("int64_t yd = wrap(y + L.c[i][1], ny);", "int64_t yd = wrap(y + L.c[i][2], ny);"),
+    "bounce_back_same_direction": ("nxt[opp[i] * N + n] = post;", "nxt[i * N + n] = post;"),
+    "force_half_missing_in_readout": ("(j[a] + (force ? 0.5 * force[a] : 0.0)) / r", "(j[a] + (force ? force[a] : 0.0)) / r"),
+    "force_not_divided_by_rho": ("sf[a] = s[a] + F[a] / rho;", "sf[a] = s[a] + F[a];"),
 }
 
 
@@ -44,6 +47,7 @@ def test_pins_catch_mutant(mutant):
                         "-lm"], check=True)
         env = dict(os.environ, LBM_ORACLE_LIB=so, OMP_NUM_THREADS="2")
         r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                            os.path.join(ROOT, "tests", "test_oracle_pins.py")], cwd=ROOT, env=env,
+                            os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                            os.path.join(ROOT, "tests", "test_oracle_walls_force.py")], cwd=ROOT, env=env,
                            capture_output=True, text=True, timeout=600)
         assert r.returncode != 0, f"mutant {mutant} survived the pins:\n{r.stdout[-2000:]}"
