@@ -83,13 +83,24 @@ typedef struct lbm_params {
     int32_t order;       /* 3 = the method (eq:3rd_order_equilibrium); 2 = without H3      */
     int32_t tensor_kind; /* LBM_TENSOR_*                                                   */
     int32_t shift_kind;  /* LBM_SHIFT_*                                                    */
-    int32_t flags;       /* reserved; must be 0                                            */
+    int32_t flags;       /* LBM_FLAG_* bits; 0 for a fully periodic fluid grid              */
     int64_t nx, ny, nz;  /* grid extents, each >= 1; nz == 1 for D2Q9; periodic on all faces */
     double tensor[9];    /* 3 x 3 row-major; leading d x d block used; must be symmetric
                             (|T - T^T| <= 1e-12 |T|) and positive definite                 */
     double tau;          /* BGK relaxation time of eq:LBE_BGK, > 1/2                       */
     double rho0;         /* reference density of the shift sigma_i, > 0 (usually 1)        */
+    double force[3];     /* body force F per cell (lattice units, momentum per step), added by
+                            the exact-difference method: f* += f^eq(rho, s + F/rho) - f^eq(rho, s);
+                            the fluid velocity is then (sum_i f_i c_i + F/2) / rho. Zero: no force.
+                            (The paper names forcing as future work, Sec. 5.) The z entry must be
+                            0 for D2Q9. */
 } lbm_params;
+
+/* lbm_params.flags bits. */
+#define LBM_FLAG_MASK 1 /* a solid mask is passed to lbm_init: cells with mask = 1 are solid and
+                           fluid cells see them through halfway bounce-back -- a population
+                           leaving x towards a solid x + c_i returns to x as c_opp(i) one step
+                           later. Solid cells carry no state (read out as zeros). */
 
 /* Host-side quantities derived from lbm_params (lbm_prepare). All FP64. */
 typedef struct lbm_derived {
@@ -113,14 +124,15 @@ typedef struct lbm_ctx lbm_ctx; /* opaque; host-side metadata only */
 int lbm_lattice_info(int32_t lattice, int32_t *q, int32_t *d, int32_t *c, double *w, int32_t *opp);
 
 /* Validate p and compute the derived quantities (host only, no device work).
- * Errors: LBM_ERR_ARG (enums, extents, rho0, flags), LBM_ERR_TAU, LBM_ERR_NOT_SPD (symmetry
+ * Errors: LBM_ERR_ARG (enums, extents, rho0, flags, force), LBM_ERR_TAU, LBM_ERR_NOT_SPD (symmetry
  * or Cholesky failure of A^-1), LBM_ERR_SIZE. out may be NULL (validation only). */
 int lbm_prepare(const lbm_params *p, lbm_derived *out);
 
 /* Bytes of one population array: q * nx * ny * nz * sizeof(storage). -1 if p is invalid. */
 int64_t lbm_pop_bytes(const lbm_params *p);
 
-/* Bytes of device scratch lbm_init needs (reduction partials). -1 if p is invalid. */
+/* Bytes of device scratch lbm_init needs (reduction partials, plus 4 bytes per cell of link
+ * words when LBM_FLAG_MASK is set). -1 if p is invalid. */
 int64_t lbm_scratch_bytes(const lbm_params *p);
 
 /* Create a context and write the initial state f_i(0, x) = f^eq_i(rho0(x), s0(x)).
@@ -129,7 +141,8 @@ int64_t lbm_scratch_bytes(const lbm_params *p);
  *   scratch:      device buffer of lbm_scratch_bytes(p), 256-byte aligned.
  *   rho0:         device FP64 [N] initial density (read during this call's device work).
  *   s0:           device FP64 [d][N] initial lattice velocity.
- *   mask:         must be NULL (solid cells are not supported by this build).
+ *   mask:         device uint8 [N], 1 = solid (read during this call's device work), required
+ *                 when p->flags has LBM_FLAG_MASK and NULL otherwise.
  *   stream:       hipStream_t for all work of this context.
  * On success *out receives the context (free with lbm_destroy). Asynchronous. */
 int lbm_init(lbm_ctx **out, const lbm_params *p, void *pop_a, void *pop_b, void *scratch, const double *rho0,
@@ -141,22 +154,25 @@ int lbm_init(lbm_ctx **out, const lbm_params *p, void *pop_a, void *pop_b, void 
 int lbm_step(lbm_ctx *ctx, int64_t nsteps);
 
 /* Moments of the current state (eq:a0discrete_f, eq:a1discrete_f).
- *   rho:    device FP64 [N] or NULL;  s: device FP64 [d][N] or NULL.
- *   totals: host FP64 [4] or NULL: sum_x rho, sum_x rho s_x, sum_x rho s_y, sum_x rho s_z
+ *   rho:    device FP64 [N] or NULL;  s: device FP64 [d][N] or NULL (the fluid velocity,
+ *           (sum_i f_i c_i + F/2) / rho). Solid cells read out rho = 0, s = 0.
+ *   totals: host FP64 [4] or NULL: sums over fluid cells of rho, rho s_x, rho s_y, rho s_z
  *           (the last zero for D2Q9), reduced on the device in FP64 in a fixed order
  *           (bit-reproducible for a given grid). Passing totals synchronises the stream and
  *           returns LBM_ERR_NONFINITE if any total is NaN or infinite. */
 int lbm_moments(lbm_ctx *ctx, double *rho, double *s, double *totals);
 
 /* Canonical pre-collision deviations g_i(t, x) = f_i(t, x) - sigma_i in the storage precision,
- * device [q][N] (lbm_pop_bytes(p) bytes), for checkpointing. Exact (a permutation). */
+ * device [q][N] (lbm_pop_bytes(p) bytes), for checkpointing. Exact (a permutation); solid
+ * cells read out as zeros. */
 int lbm_get_populations(lbm_ctx *ctx, void *out);
 
-/* Restore the state from deviations in the layout of lbm_get_populations (exact inverse).
- * The step counter is left unchanged. */
+/* Restore the state from deviations in the layout of lbm_get_populations (exact inverse;
+ * solid cells are ignored). The step counter is left unchanged. */
 int lbm_set_populations(lbm_ctx *ctx, const void *in);
 
-/* Canonical pre-collision populations f_i(t, x) = g_i + sigma_i in FP64, device [q][N]. */
+/* Canonical pre-collision populations f_i(t, x) = g_i + sigma_i in FP64, device [q][N]
+ * (zeros on solid cells). */
 int lbm_get_f64(lbm_ctx *ctx, double *out);
 
 /* Steps taken since lbm_init (-1 if ctx is NULL). */

@@ -31,6 +31,7 @@ LBM_F64, LBM_F32, LBM_F16, LBM_BF16 = 0, 1, 2, 3
 LBM_TENSOR_THETA, LBM_TENSOR_A, LBM_TENSOR_ATILDE = 0, 1, 2
 LBM_SHIFT_REST, LBM_SHIFT_WEIGHT = 0, 1
 LBM_LAUNCH_XCD_SLABS = 1
+LBM_FLAG_MASK = 1
 
 LATTICES = {"D2Q9": LBM_D2Q9, "D3Q19": LBM_D3Q19, "D3Q27": LBM_D3Q27}
 STORAGES = {"f64": LBM_F64, "f32": LBM_F32, "f16": LBM_F16, "bf16": LBM_BF16}
@@ -43,7 +44,8 @@ class lbm_params(ctypes.Structure):
     _fields_ = [("lattice", ctypes.c_int32), ("storage", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("tensor_kind", ctypes.c_int32), ("shift_kind", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64),
-                ("tensor", ctypes.c_double * 9), ("tau", ctypes.c_double), ("rho0", ctypes.c_double)]
+                ("tensor", ctypes.c_double * 9), ("tau", ctypes.c_double), ("rho0", ctypes.c_double),
+                ("force", ctypes.c_double * 3)]
 
 
 class lbm_derived(ctypes.Structure):
@@ -136,14 +138,14 @@ def lbm_lattice_info(lattice: int):
 
 
 def make_params(lattice="D3Q19", storage="f32", shape=(1, 1, 1), tensor=None, tensor_kind="theta", tau=0.8,
-                order=3, rho0=1.0, shift="rest") -> lbm_params:
+                order=3, rho0=1.0, shift="rest", force=None, masked=False) -> lbm_params:
     p = lbm_params()
     p.lattice = LATTICES[lattice] if isinstance(lattice, str) else int(lattice)
     p.storage = STORAGES[storage] if isinstance(storage, str) else int(storage)
     p.order = int(order)
     p.tensor_kind = TENSOR_KINDS[tensor_kind] if isinstance(tensor_kind, str) else int(tensor_kind)
     p.shift_kind = SHIFTS[shift] if isinstance(shift, str) else int(shift)
-    p.flags = 0
+    p.flags = LBM_FLAG_MASK if masked else 0
     nx, ny, nz = (tuple(shape) + (1, 1, 1))[:3]
     p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
     t = [1.0 / 3.0, 0, 0, 0, 1.0 / 3.0, 0, 0, 0, 1.0 / 3.0] if tensor is None else [float(v) for v in
@@ -152,6 +154,9 @@ def make_params(lattice="D3Q19", storage="f32", shape=(1, 1, 1), tensor=None, te
         p.tensor[i] = t[i]
     p.tau = float(tau)
     p.rho0 = float(rho0)
+    fv = [0.0, 0.0, 0.0] if force is None else [float(v) for v in list(force) + [0.0] * (3 - len(force))]
+    for a in range(3):
+        p.force[a] = fv[a]
     return p
 
 
@@ -244,7 +249,7 @@ class Simulation:
     f^eq(rho, s). Work goes to ``stream`` (a torch.cuda.Stream) or torch's current stream.
     """
 
-    def __init__(self, params: lbm_params, rho, s, device="cuda", stream=None):
+    def __init__(self, params: lbm_params, rho, s, device="cuda", stream=None, mask=None):
         import torch
 
         self.torch = torch
@@ -261,8 +266,11 @@ class Simulation:
         self.scratch = torch.empty(lbm_scratch_bytes(params), dtype=torch.uint8, device=self.device)
         rho_t = torch.as_tensor(rho, dtype=torch.float64).reshape(self.n).to(self.device)
         s_t = torch.as_tensor(s, dtype=torch.float64).reshape(self.d, self.n).to(self.device).contiguous()
+        mask_t = None
+        if mask is not None:
+            mask_t = torch.as_tensor(mask).reshape(self.n).to(torch.uint8).to(self.device).contiguous()
         torch.cuda.synchronize(self.device)
-        self.ctx = lbm_init(params, self.pop_a, self.pop_b, self.scratch, rho_t, s_t, None,
+        self.ctx = lbm_init(params, self.pop_a, self.pop_b, self.scratch, rho_t, s_t, mask_t,
                             self.stream.cuda_stream)
         self.stream.synchronize()  # rho_t / s_t are read by the init kernel
 

@@ -158,7 +158,10 @@ int prepare(const lbm_params *p, Prepared &out)
         return fail(LBM_ERR_ARG, "unknown tensor kind %d", p->tensor_kind);
     if (p->shift_kind != LBM_SHIFT_REST && p->shift_kind != LBM_SHIFT_WEIGHT)
         return fail(LBM_ERR_ARG, "unknown shift kind %d", p->shift_kind);
-    if (p->flags != 0) return fail(LBM_ERR_ARG, "flags must be 0");
+    if (p->flags & ~LBM_FLAG_MASK) return fail(LBM_ERR_ARG, "unknown flags 0x%x", p->flags);
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(p->force[a])) return fail(LBM_ERR_ARG, "force has a non-finite entry");
+    if (d == 2 && p->force[2] != 0.0) return fail(LBM_ERR_ARG, "D2Q9 needs force[2] == 0");
     if (p->nx < 1 || p->ny < 1 || p->nz < 1)
         return fail(LBM_ERR_ARG, "grid extents must be >= 1 (got %lld x %lld x %lld)", (long long)p->nx,
                     (long long)p->ny, (long long)p->nz);
@@ -249,7 +252,19 @@ template <typename C> StepConsts<C> consts_for(const lbm_params &p, const Prepar
         k.a[pp] = (C)(3.0 + 4.5 * ckc - 1.5 * trk);
         k.sigma[pp] = (C)dv.shift[i];
     }
+    k.forced = 0;
+    for (int a = 0; a < 3; ++a) {
+        k.force[a] = (C)p.force[a];
+        if (p.force[a] != 0.0) k.forced = 1;
+    }
     return k;
+}
+
+// Scratch layout: [link words, 4 bytes per cell, when masked][partials][totals], 256-byte
+// aligned pieces.
+int64_t links_bytes(const lbm_params &p, uint32_t n)
+{
+    return (p.flags & LBM_FLAG_MASK) ? ((int64_t)n * 4 + 255) / 256 * 256 : 0;
 }
 
 bool aligned256(const void *ptr) { return ((uintptr_t)ptr & 255u) == 0; }
@@ -264,7 +279,8 @@ struct lbm_ctx {
     StepConsts<float> k32;
     void *pop[2];
     int cur;
-    double *scratch;
+    double *partials;
+    uint32_t *links;  // null without a solid mask
     hipStream_t stream;
     int64_t t;
     int block_x, block_y;
@@ -309,9 +325,9 @@ int64_t lbm_scratch_bytes(const lbm_params *p)
     Prepared pr;
     if (prepare(p, pr)) return -1;
     Grid g{(int32_t)p->nx, (int32_t)p->ny, (int32_t)p->nz, pr.n};
-    // 4 partial sums per reduction block, then 4 totals, rounded up to 256 bytes
-    const int64_t bytes = 8 * (4 * (int64_t)moments_blocks(g) + 4);
-    return (bytes + 255) / 256 * 256;
+    // kPartials sums per reduction block, then kPartials totals, rounded up to 256 bytes
+    const int64_t bytes = 8 * (kPartials * (int64_t)moments_blocks(g) + kPartials);
+    return links_bytes(*p, pr.n) + (bytes + 255) / 256 * 256;
 }
 
 int lbm_init(lbm_ctx **out, const lbm_params *p, void *pop_a, void *pop_b, void *scratch, const double *rho0,
@@ -322,7 +338,9 @@ int lbm_init(lbm_ctx **out, const lbm_params *p, void *pop_a, void *pop_b, void 
     Prepared pr;
     int rc = prepare(p, pr);
     if (rc) return rc;
-    if (mask) return fail(LBM_ERR_UNSUPPORTED, "solid masks are not supported by this build");
+    const bool masked = p->flags & LBM_FLAG_MASK;
+    if (masked && !mask) return fail(LBM_ERR_ARG, "LBM_FLAG_MASK is set but mask is NULL");
+    if (!masked && mask) return fail(LBM_ERR_ARG, "a mask was passed without LBM_FLAG_MASK");
     if (!pop_a || !pop_b || !scratch || !rho0 || !s0) return fail(LBM_ERR_ARG, "a device pointer is NULL");
     if (pop_a == pop_b) return fail(LBM_ERR_ARG, "pop_a and pop_b must be distinct buffers");
     if (!aligned256(pop_a) || !aligned256(pop_b) || !aligned256(scratch))
@@ -337,7 +355,8 @@ int lbm_init(lbm_ctx **out, const lbm_params *p, void *pop_a, void *pop_b, void 
     c->pop[0] = pop_a;
     c->pop[1] = pop_b;
     c->cur = 0;
-    c->scratch = (double *)scratch;
+    c->links = masked ? (uint32_t *)scratch : nullptr;
+    c->partials = (double *)((char *)scratch + links_bytes(*p, pr.n));
     c->stream = (hipStream_t)stream;
     c->t = 0;
     // Work-groups span whole x rows where they fit (up to 256 cells), so the boundary cache
@@ -346,7 +365,10 @@ int lbm_init(lbm_ctx **out, const lbm_params *p, void *pop_a, void *pop_b, void 
     c->block_x = p->nx >= 256 ? 256 : (int)((p->nx + 63) / 64) * 64;
     c->block_y = 256 / c->block_x;
     c->launch_flags = 0;
-    hipError_t e = launch_init(p->lattice, p->storage, p->order, c->grid, c->k64, rho0, s0, c->pop[0], c->stream);
+    hipError_t e = hipSuccess;
+    if (masked) e = launch_links(p->lattice, c->grid, mask, c->links, c->stream);
+    if (e == hipSuccess)
+        e = launch_init(p->lattice, p->storage, p->order, c->grid, c->k64, rho0, s0, c->links, c->pop[0], c->stream);
     if (e != hipSuccess) {
         delete c;
         return fail_hip(e, "init kernel launch");
@@ -360,8 +382,9 @@ int lbm_step(lbm_ctx *c, int64_t nsteps)
     if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
     if (nsteps < 0) return fail(LBM_ERR_ARG, "nsteps must be >= 0");
     for (int64_t s = 0; s < nsteps; ++s) {
-        hipError_t e = launch_step(c->p.lattice, c->p.storage, c->p.order, c->grid, c->k64, c->k32, c->pop[c->cur],
-                                   c->pop[c->cur ^ 1], c->block_x, c->block_y, c->launch_flags, c->stream);
+        hipError_t e = launch_step(c->p.lattice, c->p.storage, c->p.order, c->grid, c->k64, c->k32, c->links,
+                                   c->pop[c->cur], c->pop[c->cur ^ 1], c->block_x, c->block_y, c->launch_flags,
+                                   c->stream);
         if (e != hipSuccess) return fail_hip(e, "step kernel launch");
         c->cur ^= 1;
         ++c->t;
@@ -373,18 +396,19 @@ int lbm_moments(lbm_ctx *c, double *rho, double *s, double *totals)
 {
     if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
     const uint32_t nb = moments_blocks(c->grid);
-    double *partials = c->scratch;
-    double *dtot = c->scratch + 4 * (size_t)nb;
-    hipError_t e = launch_moments(c->p.lattice, c->p.storage, c->grid, c->k64, c->pop[c->cur], rho, s, partials,
-                                  dtot, c->stream);
+    double *partials = c->partials;
+    double *dtot = c->partials + kPartials * (size_t)nb;
+    hipError_t e = launch_moments(c->p.lattice, c->p.storage, c->grid, c->k64, c->links, c->pop[c->cur], rho, s,
+                                  partials, dtot, c->stream);
     if (e != hipSuccess) return fail_hip(e, "moments kernel launch");
     if (!totals) return LBM_OK;
-    double h[4];
+    double h[kPartials];
     e = hipMemcpyAsync(h, dtot, sizeof h, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return fail_hip(e, "moments read-back");
-    // sum_x rho = N rho0 + sum_x (rho - rho0); the device sums the deviations
-    totals[0] = (double)c->grid.n * c->p.rho0 + h[0];
+    // sum over fluid cells of rho = (fluid cells) rho0 + sum (rho - rho0); the device sums
+    // the deviations and counts the fluid cells
+    totals[0] = h[4] * c->p.rho0 + h[0];
     totals[1] = h[1];
     totals[2] = h[2];
     totals[3] = c->pr.d == 3 ? h[3] : 0.0;
@@ -396,21 +420,24 @@ int lbm_moments(lbm_ctx *c, double *rho, double *s, double *totals)
 int lbm_get_populations(lbm_ctx *c, void *out)
 {
     if (!c || !out) return fail(LBM_ERR_ARG, "NULL argument");
-    hipError_t e = launch_permute(c->p.lattice, c->p.storage, 0, c->grid, c->k64, c->pop[c->cur], out, c->stream);
+    hipError_t e =
+        launch_permute(c->p.lattice, c->p.storage, 0, c->grid, c->k64, c->links, c->pop[c->cur], out, c->stream);
     return e == hipSuccess ? LBM_OK : fail_hip(e, "export kernel launch");
 }
 
 int lbm_set_populations(lbm_ctx *c, const void *in)
 {
     if (!c || !in) return fail(LBM_ERR_ARG, "NULL argument");
-    hipError_t e = launch_permute(c->p.lattice, c->p.storage, 1, c->grid, c->k64, in, c->pop[c->cur], c->stream);
+    hipError_t e =
+        launch_permute(c->p.lattice, c->p.storage, 1, c->grid, c->k64, c->links, in, c->pop[c->cur], c->stream);
     return e == hipSuccess ? LBM_OK : fail_hip(e, "import kernel launch");
 }
 
 int lbm_get_f64(lbm_ctx *c, double *out)
 {
     if (!c || !out) return fail(LBM_ERR_ARG, "NULL argument");
-    hipError_t e = launch_permute(c->p.lattice, c->p.storage, 2, c->grid, c->k64, c->pop[c->cur], out, c->stream);
+    hipError_t e =
+        launch_permute(c->p.lattice, c->p.storage, 2, c->grid, c->k64, c->links, c->pop[c->cur], out, c->stream);
     return e == hipSuccess ? LBM_OK : fail_hip(e, "export kernel launch");
 }
 

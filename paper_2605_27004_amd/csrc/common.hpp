@@ -31,6 +31,8 @@ template <typename C> struct StepConsts {
     C eoff[kMaxPairs + 1];  // rho0 r_p - sigma_p (zero for the rest-equilibrium shift)
     C a[kMaxPairs + 1];     // A_p of the odd part (order 3)
     C sigma[kMaxPairs + 1]; // sigma_p (read-out only)
+    C force[3];             // body force F (exact-difference method)
+    int32_t forced;         // F != 0
 };
 
 struct Grid {
@@ -41,26 +43,32 @@ struct Grid {
 // ---- launchers (kernels.hip) -----------------------------------------------------------
 // All return hipSuccess or the launch error; they enqueue on `stream` and never synchronise.
 
+// links: per-cell link words (bit 0: the cell is solid; bit i: the cell x - c_i is solid) or
+// null for a grid without solid cells.
+hipError_t launch_links(int lattice, const Grid &g, const uint8_t *mask, uint32_t *links, hipStream_t stream);
+
 hipError_t launch_init(int lattice, int storage, int order, const Grid &g, const StepConsts<double> &k,
-                       const double *rho, const double *s, void *dst, hipStream_t stream);
+                       const double *rho, const double *s, const uint32_t *links, void *dst, hipStream_t stream);
 
 // Launch flags of the step kernel (same values as LBM_LAUNCH_* in lbm.h).
 constexpr int kLaunchXcdSlabs = 1;  // XCD-contiguous tile order
 
 hipError_t launch_step(int lattice, int storage, int order, const Grid &g, const StepConsts<double> &k64,
-                       const StepConsts<float> &k32, const void *src, void *dst, int block_x, int block_y,
-                       int flags, hipStream_t stream);
+                       const StepConsts<float> &k32, const uint32_t *links, const void *src, void *dst, int block_x,
+                       int block_y, int flags, hipStream_t stream);
 
-
-// rho / s may be null. partials: scratch of 4 * nblocks doubles; totals: 4 doubles of scratch.
-hipError_t launch_moments(int lattice, int storage, const Grid &g, const StepConsts<double> &k, const void *src,
-                          double *rho, double *s, double *partials, double *totals, hipStream_t stream);
+// rho / s may be null. partials: scratch of kPartials * nblocks doubles; totals: kPartials
+// doubles of scratch (sum drho, sum rho s_x, _y, _z, fluid cells).
+constexpr int kPartials = 5;
+hipError_t launch_moments(int lattice, int storage, const Grid &g, const StepConsts<double> &k,
+                          const uint32_t *links, const void *src, double *rho, double *s, double *partials,
+                          double *totals, hipStream_t stream);
 uint32_t moments_blocks(const Grid &g);
 
-// mode 0: out[i][x] = state[i][x - c_i] (raw storage type), mode 1: the inverse scatter,
-// mode 2: out[i][x] = double(state[i][x - c_i]) + sigma_i.
+// mode 0: out[i][x] = the state's canonical g_i(x) (raw storage type), mode 1: the inverse,
+// mode 2: out[i][x] = double(g_i(x)) + sigma_i. Solid cells: zeros out / ignored in.
 hipError_t launch_permute(int lattice, int storage, int mode, const Grid &g, const StepConsts<double> &k,
-                          const void *src, void *dst, hipStream_t stream);
+                          const uint32_t *links, const void *src, void *dst, hipStream_t stream);
 
 hipError_t launch_copy(void *dst, const void *src, int64_t nbytes, hipStream_t stream);
 

@@ -237,8 +237,10 @@ __device__ inline void close_moments(C *eqp, C *eqm, C drho, C jx, C jy, C jz)
 }
 
 // One BGK collision of eq:LBE_BGK on the pre-collision deviations of a cell (rest in gp[0],
-// pair p in gp[p+1] / gm[p+1]); the arrays receive the post-collision deviations.
-template <int LAT, int ORDER, typename C>
+// pair p in gp[p+1] / gm[p+1]); the arrays receive the post-collision deviations. With FORCE
+// and k.forced set, the body force is added by the exact-difference method:
+// g* += g^eq(rho, s + F/rho) - g^eq(rho, s).
+template <int LAT, int ORDER, bool FORCE, typename C>
 __device__ inline void collide_cell(const StepConsts<C> &k, C *gp, C *gm)
 {
     constexpr int NP = Lattice<LAT>::NP;
@@ -254,6 +256,20 @@ __device__ inline void collide_cell(const StepConsts<C> &k, C *gp, C *gm)
     for (int p = 0; p < NP; ++p) {
         gp[p + 1] = fmad(k.omega, eqp[p + 1] - gp[p + 1], gp[p + 1]);
         gm[p + 1] = fmad(k.omega, eqm[p + 1] - gm[p + 1], gm[p + 1]);
+    }
+    if constexpr (FORCE) {
+        if (k.forced) {
+            const C fjx = jx + k.force[0], fjy = jy + k.force[1], fjz = jz + k.force[2];
+            C fqp[NP + 1], fqm[NP + 1];
+            equilibrium_pairs<LAT, ORDER, C>(k, drho, rho, fjx * inv, fjy * inv, fjz * inv, fqp, fqm);
+            if constexpr (sizeof(C) == 4) close_moments<LAT>(fqp, fqm, drho, fjx, fjy, fjz);
+            gp[0] += fqp[0] - eqp[0];
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                gp[p + 1] += fqp[p + 1] - eqp[p + 1];
+                gm[p + 1] += fqm[p + 1] - eqm[p + 1];
+            }
+        }
     }
 }
 
@@ -277,9 +293,34 @@ __device__ inline uint32_t tile_of(const TileMap &m, uint32_t b)
     return xcd < r ? xcd * (q + 1u) + local : r * (q + 1u) + (xcd - r) * q + local;
 }
 
-template <int LAT, typename S, int ORDER>
+// Where the canonical pre-collision population i of a cell lives in the state: normally the
+// post-collision value of the upstream cell x - c_i (pull streaming); when that cell is solid,
+// the cell's own post-collision value of the opposite direction (halfway bounce-back). The
+// link word has bit i set in the second case.
+struct Slot {
+    int plane;
+    uint32_t idx;
+};
+
+template <int LAT> __device__ inline Slot slot_plus(const Cell &c, int p, uint32_t links)
+{
+    if (links >> (2 * p + 1) & 1u) return Slot{2 * p + 2, c.own};
+    return Slot{2 * p + 1, src_plus<LAT>(c, p)};
+}
+
+template <int LAT> __device__ inline Slot slot_minus(const Cell &c, int p, uint32_t links)
+{
+    if (links >> (2 * p + 2) & 1u) return Slot{2 * p + 1, c.own};
+    return Slot{2 * p + 2, src_minus<LAT>(c, p)};
+}
+
+// Plain periodic fluid (GENERAL = false): 19 pulls, collision, 19 streaming stores per cell.
+// GENERAL = true adds the link word of each cell (solid cells return at once, links to solid
+// cells bounce back) and the body force.
+template <int LAT, typename S, int ORDER, bool GENERAL>
 __global__ __launch_bounds__(256) void k_step(const S *__restrict__ src, S *__restrict__ dst, const Grid g,
-                                              const StepConsts<typename Conv<S>::C> k, const TileMap m)
+                                              const StepConsts<typename Conv<S>::C> k, const TileMap m,
+                                              const uint32_t *__restrict__ links)
 {
     using L = Lattice<LAT>;
     using C = typename Conv<S>::C;
@@ -293,14 +334,26 @@ __global__ __launch_bounds__(256) void k_step(const S *__restrict__ src, S *__re
     const Cell c = cell_of(g, x, y, z);
 
     C gp[NP + 1], gm[NP + 1];
-    gp[0] = Conv<S>::ld(ld_at(plane(src, 0, g.n), c.own));
+    if constexpr (GENERAL) {
+        const uint32_t lk = links ? links[c.own] : 0u;
+        if (lk & 1u) return;  // solid cell: no state
+        gp[0] = Conv<S>::ld(ld_at(plane(src, 0, g.n), c.own));
 #pragma unroll
-    for (int p = 0; p < NP; ++p) {
-        gp[p + 1] = Conv<S>::ld(ld_at(plane(src, 2 * p + 1, g.n), src_plus<LAT>(c, p)));
-        gm[p + 1] = Conv<S>::ld(ld_at(plane(src, 2 * p + 2, g.n), src_minus<LAT>(c, p)));
+        for (int p = 0; p < NP; ++p) {
+            const Slot sp = slot_plus<LAT>(c, p, lk), sm = slot_minus<LAT>(c, p, lk);
+            gp[p + 1] = Conv<S>::ld(ld_at(plane(src, sp.plane, g.n), sp.idx));
+            gm[p + 1] = Conv<S>::ld(ld_at(plane(src, sm.plane, g.n), sm.idx));
+        }
+    } else {
+        gp[0] = Conv<S>::ld(ld_at(plane(src, 0, g.n), c.own));
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            gp[p + 1] = Conv<S>::ld(ld_at(plane(src, 2 * p + 1, g.n), src_plus<LAT>(c, p)));
+            gm[p + 1] = Conv<S>::ld(ld_at(plane(src, 2 * p + 2, g.n), src_minus<LAT>(c, p)));
+        }
     }
 
-    collide_cell<LAT, ORDER, C>(k, gp, gm);
+    collide_cell<LAT, ORDER, GENERAL, C>(k, gp, gm);
     st_stream(plane(dst, 0, g.n), c.own, Conv<S>::st(gp[0]));
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
@@ -309,105 +362,144 @@ __global__ __launch_bounds__(256) void k_step(const S *__restrict__ src, S *__re
     }
 }
 
-// f_i(0, x) = f^eq_i(rho(x), s(x)) in FP64, stored as a deviation at the gather position
-// x - c_i of the current buffer.
-template <int LAT, typename S, int ORDER>
-__global__ __launch_bounds__(256) void k_init(const double *__restrict__ rho_in, const double *__restrict__ s_in,
-                                              S *__restrict__ dst, const Grid g, const StepConsts<double> k)
+// Link words from a uint8 solid mask: bit 0 = the cell is solid, bit i = the cell x - c_i is.
+template <int LAT>
+__global__ __launch_bounds__(256) void k_links(const uint8_t *__restrict__ mask, uint32_t *__restrict__ links,
+                                               const Grid g)
 {
     using L = Lattice<LAT>;
+    const int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int32_t z = blockIdx.z;
+    if (x >= g.nx || y >= g.ny) return;
+    const Cell c = cell_of(g, x, y, z);
+    uint32_t w = mask[c.own] ? 1u : 0u;
+#pragma unroll
+    for (int p = 0; p < L::NP; ++p) {
+        if (mask[src_plus<LAT>(c, p)]) w |= 1u << (2 * p + 1);
+        if (mask[src_minus<LAT>(c, p)]) w |= 1u << (2 * p + 2);
+    }
+    links[c.own] = w;
+}
+
+// f_i(0, x) = f^eq_i(rho(x), s(x)) in FP64, stored as a deviation in the slot the canonical
+// gather reads for direction i at x (solid cells are skipped).
+template <int LAT, typename S, int ORDER>
+__global__ __launch_bounds__(256) void k_init(const double *__restrict__ rho_in, const double *__restrict__ s_in,
+                                              const uint32_t *__restrict__ links, S *__restrict__ dst,
+                                              const Grid g, const StepConsts<double> k)
+{
+    using L = Lattice<LAT>;
+    using C = typename Conv<S>::C;
     constexpr int NP = L::NP;
     const int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     const int32_t y = blockIdx.y * blockDim.y + threadIdx.y;
     const int32_t z = blockIdx.z;
     if (x >= g.nx || y >= g.ny) return;
     const Cell c = cell_of(g, x, y, z);
+    const uint32_t lk = links ? links[c.own] : 0u;
+    if (lk & 1u) return;
     const double rho = rho_in[c.own];
     const double sx = s_in[c.own];
     const double sy = s_in[(size_t)g.n + c.own];
     const double sz = (L::D == 3) ? s_in[2 * (size_t)g.n + c.own] : 0.0;
     double eqp[NP + 1], eqm[NP + 1];
     equilibrium_pairs<LAT, ORDER, double>(k, rho - k.rho0, rho, sx, sy, sz, eqp, eqm);
-    st_at(plane(dst, 0, g.n), c.own, Conv<S>::st((typename Conv<S>::C)eqp[0]));
+    st_at(plane(dst, 0, g.n), c.own, Conv<S>::st((C)eqp[0]));
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-        st_at(plane(dst, 2 * p + 1, g.n), src_plus<LAT>(c, p), Conv<S>::st((typename Conv<S>::C)eqp[p + 1]));
-        st_at(plane(dst, 2 * p + 2, g.n), src_minus<LAT>(c, p), Conv<S>::st((typename Conv<S>::C)eqm[p + 1]));
+        const Slot sp = slot_plus<LAT>(c, p, lk), sm = slot_minus<LAT>(c, p, lk);
+        st_at(plane(dst, sp.plane, g.n), sp.idx, Conv<S>::st((C)eqp[p + 1]));
+        st_at(plane(dst, sm.plane, g.n), sm.idx, Conv<S>::st((C)eqm[p + 1]));
     }
 }
 
 constexpr int kRedThreads = 256;
 
-// Moments of the canonical state in FP64 plus per-block partial sums of (drho, jx, jy, jz)
-// in a fixed tree order.
+// Moments of the canonical state in FP64 plus per-block partial sums of (drho, rho u_x,
+// rho u_y, rho u_z, fluid cells) in a fixed tree order; u = (j + F/2) / rho.
 template <int LAT, typename S>
-__global__ __launch_bounds__(kRedThreads) void k_moments(const S *__restrict__ src, double *__restrict__ rho_out,
-                                                         double *__restrict__ s_out, double *__restrict__ partials,
-                                                         const Grid g, const double rho0)
+__global__ __launch_bounds__(kRedThreads) void k_moments(const S *__restrict__ src, const uint32_t *__restrict__ links,
+                                                         double *__restrict__ rho_out, double *__restrict__ s_out,
+                                                         double *__restrict__ partials, const Grid g,
+                                                         const StepConsts<double> k)
 {
     using L = Lattice<LAT>;
     constexpr int NP = L::NP;
-    __shared__ double red[4][kRedThreads];
+    __shared__ double red[kPartials][kRedThreads];
     const int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     const int32_t y = blockIdx.y * blockDim.y + threadIdx.y;
     const int32_t z = blockIdx.z;
     const int tid = threadIdx.y * blockDim.x + threadIdx.x;
-    double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+    double acc[kPartials] = {0.0, 0.0, 0.0, 0.0, 0.0};
     if (x < g.nx && y < g.ny) {
         const Cell c = cell_of(g, x, y, z);
-        double gp[NP + 1], gm[NP + 1];
-        gp[0] = (double)Conv<S>::ld(ld_at(plane(src, 0, g.n), c.own));
+        const uint32_t lk = links ? links[c.own] : 0u;
+        double rho = 0.0, ux = 0.0, uy = 0.0, uz = 0.0;
+        if (!(lk & 1u)) {
+            double gp[NP + 1], gm[NP + 1];
+            gp[0] = (double)Conv<S>::ld(ld_at(plane(src, 0, g.n), c.own));
 #pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            gp[p + 1] = (double)Conv<S>::ld(ld_at(plane(src, 2 * p + 1, g.n), src_plus<LAT>(c, p)));
-            gm[p + 1] = (double)Conv<S>::ld(ld_at(plane(src, 2 * p + 2, g.n), src_minus<LAT>(c, p)));
+            for (int p = 0; p < NP; ++p) {
+                const Slot sp = slot_plus<LAT>(c, p, lk), sm = slot_minus<LAT>(c, p, lk);
+                gp[p + 1] = (double)Conv<S>::ld(ld_at(plane(src, sp.plane, g.n), sp.idx));
+                gm[p + 1] = (double)Conv<S>::ld(ld_at(plane(src, sm.plane, g.n), sm.idx));
+            }
+            double drho, jx, jy, jz;
+            moments_of<LAT>(gp, gm, drho, jx, jy, jz);
+            rho = k.rho0 + drho;
+            const double mx = jx + 0.5 * k.force[0], my = jy + 0.5 * k.force[1], mz = jz + 0.5 * k.force[2];
+            ux = mx / rho;
+            uy = my / rho;
+            uz = mz / rho;
+            acc[0] = drho;
+            acc[1] = mx;
+            acc[2] = my;
+            acc[3] = (L::D == 3) ? mz : 0.0;
+            acc[4] = 1.0;
         }
-        moments_of<LAT>(gp, gm, drho, jx, jy, jz);
-        const double rho = rho0 + drho;
         if (rho_out) rho_out[c.own] = rho;
         if (s_out) {
-            s_out[c.own] = jx / rho;
-            s_out[(size_t)g.n + c.own] = jy / rho;
-            if (L::D == 3) s_out[2 * (size_t)g.n + c.own] = jz / rho;
+            s_out[c.own] = ux;
+            s_out[(size_t)g.n + c.own] = uy;
+            if (L::D == 3) s_out[2 * (size_t)g.n + c.own] = uz;
         }
     }
-    red[0][tid] = drho;
-    red[1][tid] = jx;
-    red[2][tid] = jy;
-    red[3][tid] = jz;
+    for (int m = 0; m < kPartials; ++m) red[m][tid] = acc[m];
     __syncthreads();
     for (int h = kRedThreads / 2; h > 0; h >>= 1) {
         if (tid < h)
-            for (int m = 0; m < 4; ++m) red[m][tid] += red[m][tid + h];
+            for (int m = 0; m < kPartials; ++m) red[m][tid] += red[m][tid + h];
         __syncthreads();
     }
-    if (tid < 4) {
+    if (tid < kPartials) {
         const uint32_t b = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-        partials[4 * (size_t)b + tid] = red[tid][0];
+        partials[kPartials * (size_t)b + tid] = red[tid][0];
     }
 }
 
 __global__ __launch_bounds__(kRedThreads) void k_reduce_partials(const double *__restrict__ partials, uint32_t nblocks,
                                                                  double *__restrict__ totals)
 {
-    __shared__ double red[4][kRedThreads];
+    __shared__ double red[kPartials][kRedThreads];
     const int tid = threadIdx.x;
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    double acc[kPartials] = {0.0, 0.0, 0.0, 0.0, 0.0};
     for (uint32_t b = tid; b < nblocks; b += kRedThreads)
-        for (int m = 0; m < 4; ++m) acc[m] += partials[4 * (size_t)b + m];
-    for (int m = 0; m < 4; ++m) red[m][tid] = acc[m];
+        for (int m = 0; m < kPartials; ++m) acc[m] += partials[kPartials * (size_t)b + m];
+    for (int m = 0; m < kPartials; ++m) red[m][tid] = acc[m];
     __syncthreads();
     for (int h = kRedThreads / 2; h > 0; h >>= 1) {
         if (tid < h)
-            for (int m = 0; m < 4; ++m) red[m][tid] += red[m][tid + h];
+            for (int m = 0; m < kPartials; ++m) red[m][tid] += red[m][tid + h];
         __syncthreads();
     }
-    if (tid < 4) totals[tid] = red[tid][0];
+    if (tid < kPartials) totals[tid] = red[tid][0];
 }
 
-// Canonical-order permutations of the state (see the file header).
+// Canonical-order permutations of the state (see the file header and Slot).
 template <int LAT, typename S, int MODE>
-__global__ __launch_bounds__(256) void k_permute(const void *__restrict__ in, void *__restrict__ out, const Grid g,
+__global__ __launch_bounds__(256) void k_permute(const void *__restrict__ in, void *__restrict__ out,
+                                                 const uint32_t *__restrict__ links, const Grid g,
                                                  const StepConsts<double> k)
 {
     using L = Lattice<LAT>;
@@ -417,21 +509,24 @@ __global__ __launch_bounds__(256) void k_permute(const void *__restrict__ in, vo
     const int32_t z = blockIdx.z;
     if (x >= g.nx || y >= g.ny) return;
     const Cell c = cell_of(g, x, y, z);
-    auto move = [&](int i, uint32_t state_idx, double sigma) {
+    const uint32_t lk = links ? links[c.own] : 0u;
+    const bool solid = lk & 1u;
+    auto move = [&](int i, Slot sl, double sigma) {
         if constexpr (MODE == 0) {
-            st_at(plane((S *)out, i, g.n), c.own, ld_at(plane((const S *)in, i, g.n), state_idx));
+            st_at(plane((S *)out, i, g.n), c.own,
+                  solid ? Conv<S>::st(typename Conv<S>::C(0)) : ld_at(plane((const S *)in, sl.plane, g.n), sl.idx));
         } else if constexpr (MODE == 1) {
-            st_at(plane((S *)out, i, g.n), state_idx, ld_at(plane((const S *)in, i, g.n), c.own));
+            if (!solid) st_at(plane((S *)out, sl.plane, g.n), sl.idx, ld_at(plane((const S *)in, i, g.n), c.own));
         } else {
-            const double v = (double)Conv<S>::ld(ld_at(plane((const S *)in, i, g.n), state_idx));
-            st_at(plane((double *)out, i, g.n), c.own, v + sigma);
+            const double v = solid ? 0.0 : (double)Conv<S>::ld(ld_at(plane((const S *)in, sl.plane, g.n), sl.idx)) + sigma;
+            st_at(plane((double *)out, i, g.n), c.own, v);
         }
     };
-    move(0, c.own, k.sigma[0]);
+    move(0, Slot{0, c.own}, k.sigma[0]);
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-        move(2 * p + 1, src_plus<LAT>(c, p), k.sigma[p + 1]);
-        move(2 * p + 2, src_minus<LAT>(c, p), k.sigma[p + 1]);
+        move(2 * p + 1, slot_plus<LAT>(c, p, lk), k.sigma[p + 1]);
+        move(2 * p + 2, slot_minus<LAT>(c, p, lk), k.sigma[p + 1]);
     }
 }
 
@@ -476,8 +571,18 @@ constexpr int kBlockY = 4;
 
 }  // namespace
 
+hipError_t launch_links(int lattice, const Grid &g, const uint8_t *mask, uint32_t *links, hipStream_t stream)
+{
+    return by_lattice(lattice, [&](auto lat) {
+        constexpr int LAT = decltype(lat)::value;
+        const dim3 grid = cell_grid(g, kBlockX, kBlockY), block(kBlockX, kBlockY);
+        hipLaunchKernelGGL((k_links<LAT>), grid, block, 0, stream, mask, links, g);
+        return hipGetLastError();
+    });
+}
+
 hipError_t launch_init(int lattice, int storage, int order, const Grid &g, const StepConsts<double> &k,
-                       const double *rho, const double *s, void *dst, hipStream_t stream)
+                       const double *rho, const double *s, const uint32_t *links, void *dst, hipStream_t stream)
 {
     return by_lattice(lattice, [&](auto lat) {
         return by_storage(storage, [&](auto sv) {
@@ -485,17 +590,17 @@ hipError_t launch_init(int lattice, int storage, int order, const Grid &g, const
             constexpr int LAT = decltype(lat)::value;
             const dim3 grid = cell_grid(g, kBlockX, kBlockY), block(kBlockX, kBlockY);
             if (order == 2)
-                hipLaunchKernelGGL((k_init<LAT, S, 2>), grid, block, 0, stream, rho, s, (S *)dst, g, k);
+                hipLaunchKernelGGL((k_init<LAT, S, 2>), grid, block, 0, stream, rho, s, links, (S *)dst, g, k);
             else
-                hipLaunchKernelGGL((k_init<LAT, S, 3>), grid, block, 0, stream, rho, s, (S *)dst, g, k);
+                hipLaunchKernelGGL((k_init<LAT, S, 3>), grid, block, 0, stream, rho, s, links, (S *)dst, g, k);
             return hipGetLastError();
         });
     });
 }
 
 hipError_t launch_step(int lattice, int storage, int order, const Grid &g, const StepConsts<double> &k64,
-                       const StepConsts<float> &k32, const void *src, void *dst, int block_x, int block_y,
-                       int flags, hipStream_t stream)
+                       const StepConsts<float> &k32, const uint32_t *links, const void *src, void *dst, int block_x,
+                       int block_y, int flags, hipStream_t stream)
 {
     return by_lattice(lattice, [&](auto lat) {
         return by_storage(storage, [&](auto sv) {
@@ -511,10 +616,20 @@ hipError_t launch_step(int lattice, int storage, int order, const Grid &g, const
             m.nblocks = g3.x * g3.y * g3.z;
             m.xcd_slabs = (flags & kLaunchXcdSlabs) ? 1u : 0u;
             const dim3 grid(m.nblocks);
-            if (order == 2)
-                hipLaunchKernelGGL((k_step<LAT, S, 2>), grid, block, 0, stream, (const S *)src, (S *)dst, g, *kc, m);
-            else
-                hipLaunchKernelGGL((k_step<LAT, S, 3>), grid, block, 0, stream, (const S *)src, (S *)dst, g, *kc, m);
+            const bool general = links != nullptr || kc->forced;
+            const S *in = (const S *)src;
+            S *out = (S *)dst;
+            if (order == 2) {
+                if (general)
+                    hipLaunchKernelGGL((k_step<LAT, S, 2, true>), grid, block, 0, stream, in, out, g, *kc, m, links);
+                else
+                    hipLaunchKernelGGL((k_step<LAT, S, 2, false>), grid, block, 0, stream, in, out, g, *kc, m, links);
+            } else {
+                if (general)
+                    hipLaunchKernelGGL((k_step<LAT, S, 3, true>), grid, block, 0, stream, in, out, g, *kc, m, links);
+                else
+                    hipLaunchKernelGGL((k_step<LAT, S, 3, false>), grid, block, 0, stream, in, out, g, *kc, m, links);
+            }
             return hipGetLastError();
         });
     });
@@ -526,16 +641,17 @@ uint32_t moments_blocks(const Grid &g)
     return grid.x * grid.y * grid.z;
 }
 
-hipError_t launch_moments(int lattice, int storage, const Grid &g, const StepConsts<double> &k, const void *src,
-                          double *rho, double *s, double *partials, double *totals, hipStream_t stream)
+hipError_t launch_moments(int lattice, int storage, const Grid &g, const StepConsts<double> &k,
+                          const uint32_t *links, const void *src, double *rho, double *s, double *partials,
+                          double *totals, hipStream_t stream)
 {
     return by_lattice(lattice, [&](auto lat) {
         return by_storage(storage, [&](auto sv) {
             using S = decltype(sv);
             constexpr int LAT = decltype(lat)::value;
             const dim3 grid = cell_grid(g, kBlockX, kRedThreads / kBlockX), block(kBlockX, kRedThreads / kBlockX);
-            hipLaunchKernelGGL((k_moments<LAT, S>), grid, block, 0, stream, (const S *)src, rho, s, partials, g,
-                               k.rho0);
+            hipLaunchKernelGGL((k_moments<LAT, S>), grid, block, 0, stream, (const S *)src, links, rho, s, partials, g,
+                               k);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kRedThreads), 0, stream, partials,
@@ -546,7 +662,7 @@ hipError_t launch_moments(int lattice, int storage, const Grid &g, const StepCon
 }
 
 hipError_t launch_permute(int lattice, int storage, int mode, const Grid &g, const StepConsts<double> &k,
-                          const void *src, void *dst, hipStream_t stream)
+                          const uint32_t *links, const void *src, void *dst, hipStream_t stream)
 {
     return by_lattice(lattice, [&](auto lat) {
         return by_storage(storage, [&](auto sv) {
@@ -554,11 +670,11 @@ hipError_t launch_permute(int lattice, int storage, int mode, const Grid &g, con
             constexpr int LAT = decltype(lat)::value;
             const dim3 grid = cell_grid(g, kBlockX, kBlockY), block(kBlockX, kBlockY);
             if (mode == 0)
-                hipLaunchKernelGGL((k_permute<LAT, S, 0>), grid, block, 0, stream, src, dst, g, k);
+                hipLaunchKernelGGL((k_permute<LAT, S, 0>), grid, block, 0, stream, src, dst, links, g, k);
             else if (mode == 1)
-                hipLaunchKernelGGL((k_permute<LAT, S, 1>), grid, block, 0, stream, src, dst, g, k);
+                hipLaunchKernelGGL((k_permute<LAT, S, 1>), grid, block, 0, stream, src, dst, links, g, k);
             else
-                hipLaunchKernelGGL((k_permute<LAT, S, 2>), grid, block, 0, stream, src, dst, g, k);
+                hipLaunchKernelGGL((k_permute<LAT, S, 2>), grid, block, 0, stream, src, dst, links, g, k);
             return hipGetLastError();
         });
     });

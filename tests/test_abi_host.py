@@ -96,7 +96,8 @@ def test_prepare_weight_shift_and_diagnostic():
     (lambda p: setattr(p, "order", 4), lbm.LBM_ERR_ARG),
     (lambda p: setattr(p, "tensor_kind", 5), lbm.LBM_ERR_ARG),
     (lambda p: setattr(p, "shift_kind", 2), lbm.LBM_ERR_ARG),
-    (lambda p: setattr(p, "flags", 1), lbm.LBM_ERR_ARG),
+    (lambda p: setattr(p, "flags", 2), lbm.LBM_ERR_ARG),
+    (lambda p: p.force.__setitem__(1, float("nan")), lbm.LBM_ERR_ARG),
     (lambda p: setattr(p, "nx", 0), lbm.LBM_ERR_ARG),
     (lambda p: setattr(p, "nz", -3), lbm.LBM_ERR_ARG),
     (lambda p: setattr(p, "tau", 0.5), lbm.LBM_ERR_TAU),
@@ -137,7 +138,17 @@ def test_size_limit_is_per_plane_bytes():
 def test_sizes():
     p = lbm.make_params("D3Q19", "f32", (256, 256, 256), W.config2_theta(0), "theta", 0.7)
     assert lbm.lbm_pop_bytes(p) == 19 * 256 ** 3 * 4
-    assert lbm.lbm_scratch_bytes(p) % 256 == 0 and lbm.lbm_scratch_bytes(p) >= 8 * 4 * (256 ** 3 // 256)
+    plain = lbm.lbm_scratch_bytes(p)
+    assert plain % 256 == 0 and plain >= 8 * 5 * (256 ** 3 // 256)
+    pm = lbm.make_params("D3Q19", "f32", (256, 256, 256), W.config2_theta(0), "theta", 0.7, masked=True)
+    assert lbm.lbm_scratch_bytes(pm) == plain + 4 * 256 ** 3     # link words
+
+
+def test_d2q9_rejects_z_force():
+    p = lbm.make_params("D2Q9", "f64", (8, 8, 1), W.config1_theta(), "theta", 0.8, force=[0, 0, 1e-6])
+    with pytest.raises(lbm.LBMError) as ei:
+        lbm.lbm_prepare(p)
+    assert ei.value.code == lbm.LBM_ERR_ARG
 
 
 def test_init_rejects_before_any_device_work():
@@ -148,7 +159,7 @@ def test_init_rejects_before_any_device_work():
         (dict(pop_b=a), lbm.LBM_ERR_ARG),
         (dict(pop_a=a + 4), lbm.LBM_ERR_ALIGN),
         (dict(scratch=s + 128), lbm.LBM_ERR_ALIGN),
-        (dict(mask=4 << 20), lbm.LBM_ERR_UNSUPPORTED),
+        (dict(mask=4 << 20), lbm.LBM_ERR_ARG),        # a mask without LBM_FLAG_MASK
     ]
     for over, code in cases:
         kw = dict(pop_a=a, pop_b=b, scratch=s, rho0=4 << 20, s0=5 << 20, mask=None, stream=None)
@@ -160,6 +171,10 @@ def test_init_rejects_before_any_device_work():
     with pytest.raises(lbm.LBMError) as ei:
         lbm.lbm_init(bad, a, b, s, 4 << 20, 5 << 20)
     assert ei.value.code == lbm.LBM_ERR_TAU
+    masked = lbm.make_params("D3Q19", "f32", (8, 8, 8), W.config2_theta(0), "theta", 0.7, masked=True)
+    with pytest.raises(lbm.LBMError) as ei:
+        lbm.lbm_init(masked, a, b, s, 4 << 20, 5 << 20, mask=None)   # flag set, mask missing
+    assert ei.value.code == lbm.LBM_ERR_ARG
 
 
 def test_null_context_calls_fail_cleanly():

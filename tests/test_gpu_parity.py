@@ -21,74 +21,13 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 lbm = pytest.importorskip("paper_2605_27004_amd")
 
-TOL = {"f64": 1e-12, "f32": 1e-5}
+from tests.gpu_common import TOL, _log, _perm, check, errors, gpu_run, oracle_run  # noqa: E402
 
 
 @pytest.fixture(scope="module", autouse=True)
 def _need_gpu():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-
-
-def _perm(name):
-    """perm[i] = oracle index of the library's canonical direction i."""
-    _, _, c, _, _ = lbm.lbm_lattice_info(lbm.LATTICES[name])
-    oc, _, _ = oracle.lattice(name)
-    idx = {tuple(v): i for i, v in enumerate(oc.tolist())}
-    return np.array([idx[tuple(v)] for v in c])
-
-
-def gpu_run(wl, storage, steps, order=None, shift="rest", block=None, chunks=1):
-    order = wl.order if order is None else order
-    p = lbm.make_params(wl.lattice, storage, wl.shape, wl.tensor, wl.tensor_kind, wl.tau, order, shift=shift)
-    sim = lbm.Simulation(p, wl.rho, wl.s)
-    if block:
-        sim.set_launch(*block)
-    left = steps
-    for _ in range(chunks):
-        k = left // chunks if chunks > 1 else left
-        sim.step(k)
-        left -= k
-    sim.step(left)
-    rho, s, tot = sim.moments()
-    f = sim.f64()
-    torch.cuda.synchronize()
-    out = dict(f=f.cpu().numpy(), rho=rho.cpu().numpy(), s=s.cpu().numpy(), totals=tot, t=sim.t, sim=sim)
-    return out
-
-
-def oracle_run(wl, steps, order=None):
-    order = wl.order if order is None else order
-    f, rho, s = oracle.run(wl.lattice, wl.shape, wl.tensor, wl.tensor_kind, wl.tau, wl.rho, wl.s, steps, order)
-    return dict(f=f[_perm(wl.lattice)], rho=rho, s=s)
-
-
-def errors(g, o, u0):
-    return dict(f=np.abs(g["f"] - o["f"]).max() / np.abs(o["f"]).max(),
-                rho=np.abs(g["rho"] - o["rho"]).max() / np.abs(o["rho"]).max(),
-                s=np.abs(g["s"] - o["s"]).max() / u0)
-
-
-def check(wl, storage, steps, order=None, **kw):
-    print(f"[parity] {wl.lattice} {wl.shape} {storage} order={order or wl.order} steps={steps}", flush=True)
-    g = gpu_run(wl, storage, steps, order, **kw)
-    o = oracle_run(wl, steps, order)
-    e = errors(g, o, wl.u0)
-    print(f"[parity] errors {e}", flush=True)
-    _log(dict(lattice=wl.lattice, shape=list(wl.shape), storage=storage, order=order or wl.order, steps=steps,
-              shift=kw.get("shift", "rest"), reference="oracle", **{k: float(v) for k, v in e.items()}))
-    assert g["t"] == steps
-    for k, v in e.items():
-        assert v <= TOL[storage], (k, v)
-    return g, o, e
-
-
-def _log(rec):
-    """Append one error record to $PARITY_LOG (JSON lines) when it is set."""
-    path = os.environ.get("PARITY_LOG")
-    if path:
-        with open(path, "a") as fh:
-            fh.write(json.dumps(rec) + "\n")
 
 
 def _random_wl(lattice, shape, seed, tau=0.75, order=3):

@@ -40,7 +40,8 @@ class Workload:
     steps: int
     rho: np.ndarray         # [N]
     s: np.ndarray           # [d][N]
-    u0: float               # initial velocity amplitude (normalises velocity errors)
+    u0: float | None        # initial velocity amplitude (normalises velocity errors); None when
+    #                         the flow starts at rest
     order: int = 3
     name: str = ""
     meta: dict = field(default_factory=dict)
@@ -184,6 +185,64 @@ def config2(n: int = 256, steps: int = 1000, seed: int = 0, lattice: str = "D3Q1
 
 def config3_theta() -> np.ndarray:
     return CS2 * np.diag([1.5, 1.0, 0.5])
+
+
+def porous_mask(shape, seed: int = 0, solid_fraction: float = 0.40, axes=(4.0, 16.0)) -> np.ndarray:
+    """Seeded solid mask (uint8 [N], 1 = solid) of overlapping random ellipsoids on a periodic box.
+
+    Each ellipsoid draws, in this order: its centre (uniform in the box), three semi-axes
+    (uniform in `axes`) and a Haar-random orientation (QR of a normal 3 x 3 matrix, signs fixed
+    by diag(R)). Distances use the periodic minimum image. Ellipsoids are added until the
+    solid fraction reaches `solid_fraction`.
+    """
+    nx, ny, nz = shape
+    n = nx * ny * nz
+    solid = np.zeros((nz, ny, nx), dtype=bool)
+    rng = np.random.default_rng(seed)
+    count = 0
+    dims = np.array([nx, ny, nz], dtype=np.float64)
+    while count < solid_fraction * n:
+        centre = rng.uniform(0.0, 1.0, 3) * dims
+        semi = rng.uniform(axes[0], axes[1], 3)
+        q, r = np.linalg.qr(rng.normal(size=(3, 3)))
+        q = q * np.sign(np.diag(r))
+        reach = int(np.ceil(semi.max()))
+        idx = []
+        for a in range(3):
+            size = int(dims[a])
+            if 2 * reach + 2 >= size:
+                idx.append(np.arange(size))      # the window covers the axis: each cell once
+            else:
+                lo = int(np.floor(centre[a])) - reach
+                idx.append(np.arange(lo, lo + 2 * reach + 2))
+        # minimum-image offsets of the candidate cells from the centre, per axis
+        off = [((idx[a] - centre[a] + dims[a] / 2) % dims[a]) - dims[a] / 2 for a in range(3)]
+        oz, oy, ox = np.meshgrid(off[2], off[1], off[0], indexing="ij")
+        rel = np.stack([ox, oy, oz], axis=-1) @ q           # coordinates in the ellipsoid frame
+        inside = ((rel / semi) ** 2).sum(axis=-1) <= 1.0
+        zz, yy, xx = np.meshgrid(idx[2] % nz, idx[1] % ny, idx[0] % nx, indexing="ij")
+        sel = inside & ~solid[zz, yy, xx]
+        solid[zz[sel], yy[sel], xx[sel]] = True
+        count += int(sel.sum())
+    return solid.reshape(n).astype(np.uint8)
+
+
+def config3(n: int = 512, steps: int = 1000, seed: int = 0) -> Workload:
+    """D3Q27 n^3 porous medium: ellipsoid mask (porosity 0.6, semi-axes 4-16 cells), halfway
+    bounce-back, body force 1e-6 along x, tensor cs^2 diag(1.5, 1, 0.5), tau = 0.9, rho = 1, s = 0."""
+    shape = (n, n, n)
+    rho, s = uniform_fields(shape, 3)
+    wl = Workload("D3Q27", shape, config3_theta(), "theta", 0.9, steps, rho, s, None, name="d3q27_porous",
+                  meta={"seed": seed})
+    wl.meta["mask"] = porous_mask(shape, seed)
+    wl.meta["force"] = np.array([1e-6, 0.0, 0.0])
+    return wl
+
+
+def channel_mask(shape, wall_axis: int = 1) -> np.ndarray:
+    """Solid planes at index 0 and n-1 along `wall_axis` (a plane channel), uint8 [N]."""
+    x = grid(shape)[wall_axis]
+    return ((x == 0) | (x == shape[wall_axis] - 1)).astype(np.uint8)
 
 
 def e1_taylor_green(a_xy: float, order: int, n: int = 64) -> Workload:
