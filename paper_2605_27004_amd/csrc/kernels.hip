@@ -259,6 +259,8 @@ __device__ inline void collide_cell(const StepConsts<C> &k, C *gp, C *gm)
     }
     if constexpr (FORCE) {
         if (k.forced) {
+            // both equilibria closed (in FP32) on their own momenta, j + F and j, so the
+            // increment carries exactly F and no mass
             const C fjx = jx + k.force[0], fjy = jy + k.force[1], fjz = jz + k.force[2];
             C fqp[NP + 1], fqm[NP + 1];
             equilibrium_pairs<LAT, ORDER, C>(k, drho, rho, fjx * inv, fjy * inv, fjz * inv, fqp, fqm);
@@ -335,14 +337,22 @@ __global__ __launch_bounds__(256) void k_step(const S *__restrict__ src, S *__re
 
     C gp[NP + 1], gm[NP + 1];
     if constexpr (GENERAL) {
+        // A solid cell has no state and none of its slots is ever read (links route around
+        // it), but its lane still stores zeros so that every store of the wave covers whole
+        // cache lines; partial-line stores along solid boundaries measured far slower.
         const uint32_t lk = links ? links[c.own] : 0u;
-        if (lk & 1u) return;  // solid cell: no state
-        gp[0] = Conv<S>::ld(ld_at(plane(src, 0, g.n), c.own));
+        if (lk & 1u) {
 #pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            const Slot sp = slot_plus<LAT>(c, p, lk), sm = slot_minus<LAT>(c, p, lk);
-            gp[p + 1] = Conv<S>::ld(ld_at(plane(src, sp.plane, g.n), sp.idx));
-            gm[p + 1] = Conv<S>::ld(ld_at(plane(src, sm.plane, g.n), sm.idx));
+            for (int p = 0; p <= NP; ++p) gp[p] = gm[p] = C(0);
+        } else {
+            gp[0] = Conv<S>::ld(ld_at(plane(src, 0, g.n), c.own));
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                const Slot sp = slot_plus<LAT>(c, p, lk), sm = slot_minus<LAT>(c, p, lk);
+                gp[p + 1] = Conv<S>::ld(ld_at(plane(src, sp.plane, g.n), sp.idx));
+                gm[p + 1] = Conv<S>::ld(ld_at(plane(src, sm.plane, g.n), sm.idx));
+            }
+            collide_cell<LAT, ORDER, true, C>(k, gp, gm);
         }
     } else {
         gp[0] = Conv<S>::ld(ld_at(plane(src, 0, g.n), c.own));
@@ -353,7 +363,7 @@ __global__ __launch_bounds__(256) void k_step(const S *__restrict__ src, S *__re
         }
     }
 
-    collide_cell<LAT, ORDER, GENERAL, C>(k, gp, gm);
+    if constexpr (!GENERAL) collide_cell<LAT, ORDER, false, C>(k, gp, gm);
     st_stream(plane(dst, 0, g.n), c.own, Conv<S>::st(gp[0]));
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
@@ -398,7 +408,10 @@ __global__ __launch_bounds__(256) void k_init(const double *__restrict__ rho_in,
     if (x >= g.nx || y >= g.ny) return;
     const Cell c = cell_of(g, x, y, z);
     const uint32_t lk = links ? links[c.own] : 0u;
-    if (lk & 1u) return;
+    if (lk & 1u) {  // solid: no state; its own slots are set to zero like every step does
+        for (int i = 0; i < L::Q; ++i) st_at(plane(dst, i, g.n), c.own, Conv<S>::st(C(0)));
+        return;
+    }
     const double rho = rho_in[c.own];
     const double sx = s_in[c.own];
     const double sy = s_in[(size_t)g.n + c.own];
