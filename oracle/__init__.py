@@ -57,11 +57,16 @@ def _load():
                               ctypes.c_int]
     lib.orc_steps_ext.argtypes = [ctypes.c_int, ctypes.c_int, _i64, _i64, _i64, _dp, ctypes.c_double, _i64, _dp,
                                   _u8p, _dp, ctypes.c_int]
+    lib.orc_steps_gray.argtypes = [ctypes.c_int, ctypes.c_int, _i64, _i64, _i64, _dp, ctypes.c_double, _i64, _dp,
+                                   _u8p, _dp, _dp, ctypes.c_int]
+    lib.orc_objective.argtypes = [ctypes.c_int, _i64, _i64, _i64, _dp, _u8p, _dp, ctypes.c_int, _i64]
+    lib.orc_objective.restype = ctypes.c_double
     lib.orc_moments.argtypes = [ctypes.c_int, _i64, _dp, _dp, _dp]
     lib.orc_moments_ext.argtypes = [ctypes.c_int, _i64, _dp, _u8p, _dp, _dp, _dp]
     lib.orc_num_threads.argtypes = []
     for name in ("orc_gh1d", "orc_lattice", "orc_tensor_to_ainv", "orc_feq", "orc_init", "orc_init_ext",
-                 "orc_steps", "orc_steps_ext", "orc_moments", "orc_moments_ext", "orc_num_threads"):
+                 "orc_steps", "orc_steps_ext", "orc_steps_gray", "orc_moments", "orc_moments_ext",
+                 "orc_num_threads"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -181,6 +186,31 @@ def steps(name: str, shape, ainv, tau: float, f: np.ndarray, nsteps: int, order:
     if rc:
         raise RuntimeError(f"orc_steps failed ({rc})")
     return f
+
+
+def steps_gray(name: str, shape, ainv, tau: float, f: np.ndarray, nsteps: int, gray, order: int = 3,
+               force=None, nthreads: int = 0) -> np.ndarray:
+    """Like :func:`steps` with a gray mask m ([N], in [0, 1]): f* = (1 - m) f^BGK + m f_opp."""
+    nx, ny, nz = _shape3(shape)
+    d = dim(name)
+    a = np.ascontiguousarray(np.asarray(ainv, dtype=np.float64)[:d, :d])
+    gm = np.ascontiguousarray(np.asarray(gray, dtype=np.float64).reshape(nx * ny * nz))
+    fp, _keep_f = _force_ptr(force, d)
+    rc = _load().orc_steps_gray(LATTICES[name], int(order), nx, ny, nz, _ptr(a), float(tau), int(nsteps), _ptr(f),
+                                None, _ptr(gm), fp, int(nthreads))
+    if rc:
+        raise RuntimeError(f"orc_steps_gray failed ({rc})")
+    return f
+
+
+def objective(name: str, shape, f: np.ndarray, kind: int, plane: int = 0, mask=None, force=None) -> float:
+    """Outlet mass flux (kind 0, plane x = plane) or kinetic energy (kind 1) of a state."""
+    nx, ny, nz = _shape3(shape)
+    d = dim(name)
+    mp, _keep_m = _mask_ptr(mask, nx * ny * nz)
+    fp, _keep_f = _force_ptr(force, d)
+    return float(_load().orc_objective(LATTICES[name], nx, ny, nz, _ptr(np.ascontiguousarray(f)), mp, fp, int(kind),
+                                       int(plane)))
 
 
 def moments(name: str, f: np.ndarray, mask=None, force=None):

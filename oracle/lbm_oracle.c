@@ -34,6 +34,10 @@
  *   - solid cells (mask = 1) carry no populations (kept at zero); a population leaving a fluid
  *     cell x towards a solid cell x + c_i returns to x in the opposite direction at the next
  *     step (halfway bounce-back): f_opp(i)(t+1, x) = f*_i(t, x);
+ *   - gray cells (a fraction m in [0, 1] per cell, for differentiable obstacles): the
+ *     post-collision populations are (1 - m) times the BGK result plus m times the cell's own
+ *     pre-collision population of the opposite direction, f*_i = (1 - m) f^BGK_i + m f_opp(i),
+ *     then streamed as usual (m = 1 reflects everything back on the node);
  *   - body force F (momentum per cell per step) by the exact-difference method:
  *     f*_i = f_i + (f^eq_i(rho, s) - f_i)/tau + [f^eq_i(rho, s + F/rho) - f^eq_i(rho, s)],
  *     with s = sum_i f_i c_i / rho, and the fluid velocity read out as (sum_i f_i c_i + F/2)/rho.
@@ -319,8 +323,9 @@ static int64_t wrap(int64_t v, int64_t n)
 /* nsteps of eq:LBE_BGK on the periodic grid; f ([q][N]) holds the pre-collision state and
  * is advanced in place (a second array is allocated here). mask ([N], 1 = solid) and force
  * ([d]) may be NULL; see the header for their definitions. */
-int orc_steps_ext(int lattice, int order, int64_t nx, int64_t ny, int64_t nz, const double *Ainv, double tau,
-                  int64_t nsteps, double *f, const uint8_t *mask, const double *force, int nthreads)
+int orc_steps_gray(int lattice, int order, int64_t nx, int64_t ny, int64_t nz, const double *Ainv, double tau,
+                   int64_t nsteps, double *f, const uint8_t *mask, const double *gray, const double *force,
+                   int nthreads)
 {
     lattice_t L;
     if (build_lattice(lattice, &L)) return -1;
@@ -367,10 +372,12 @@ int orc_steps_ext(int lattice, int order, int64_t nx, int64_t ny, int64_t nz, co
                         for (int a = 0; a < d; ++a) sf[a] = s[a] + F[a] / rho;
                         feq_cell(&L, order, K, rho, sf, feqf);
                     }
+                    const double m = gray ? gray[n] : 0.0;
                     for (int i = 0; i < q; ++i) {
                         double fi = cur[i * N + n];
                         double post = fi + (feq[i] - fi) / tau;
                         if (forced) post += feqf[i] - feq[i];
+                        if (gray) post = (1.0 - m) * post + m * cur[opp[i] * N + n];
                         int64_t xd = wrap(x + L.c[i][0], nx);
                         int64_t yd = wrap(y + L.c[i][1], ny);
                         int64_t zd = wrap(z + L.c[i][2], nz);
@@ -390,10 +397,16 @@ int orc_steps_ext(int lattice, int order, int64_t nx, int64_t ny, int64_t nz, co
     return 0;
 }
 
+int orc_steps_ext(int lattice, int order, int64_t nx, int64_t ny, int64_t nz, const double *Ainv, double tau,
+                  int64_t nsteps, double *f, const uint8_t *mask, const double *force, int nthreads)
+{
+    return orc_steps_gray(lattice, order, nx, ny, nz, Ainv, tau, nsteps, f, mask, NULL, force, nthreads);
+}
+
 int orc_steps(int lattice, int order, int64_t nx, int64_t ny, int64_t nz, const double *Ainv, double tau,
               int64_t nsteps, double *f, int nthreads)
 {
-    return orc_steps_ext(lattice, order, nx, ny, nz, Ainv, tau, nsteps, f, NULL, NULL, nthreads);
+    return orc_steps_gray(lattice, order, nx, ny, nz, Ainv, tau, nsteps, f, NULL, NULL, NULL, nthreads);
 }
 
 /* rho = sum_i f_i, s = (sum_i f_i c_i + F/2) / rho (F = 0 when force is NULL); solid cells
@@ -425,4 +438,37 @@ int orc_moments_ext(int lattice, int64_t N, const double *f, const uint8_t *mask
 int orc_moments(int lattice, int64_t N, const double *f, double *rho, double *s)
 {
     return orc_moments_ext(lattice, N, f, NULL, NULL, rho, s);
+}
+
+/* Objectives of the final state (used by gradient checks):
+ *   kind 0: mass flux through the plane x = plane, sum over its cells of (j_x + F_x/2);
+ *   kind 1: kinetic energy, sum over all cells of |j + F/2|^2 / (2 rho).
+ * Solid cells of a binary mask are skipped. */
+double orc_objective(int lattice, int64_t nx, int64_t ny, int64_t nz, const double *f, const uint8_t *mask,
+                     const double *force, int kind, int64_t plane)
+{
+    lattice_t L;
+    if (build_lattice(lattice, &L)) return NAN;
+    const int64_t N = nx * ny * nz;
+    double total = 0.0;
+    for (int64_t n = 0; n < N; ++n) {
+        if (mask && mask[n]) continue;
+        const int64_t x = n % nx;
+        if (kind == 0 && x != plane) continue;
+        double r = 0.0, j[3] = {0.0, 0.0, 0.0};
+        for (int i = 0; i < L.q; ++i) {
+            double fi = f[i * N + n];
+            r += fi;
+            for (int a = 0; a < L.d; ++a) j[a] += fi * L.c[i][a];
+        }
+        for (int a = 0; a < L.d; ++a) j[a] += force ? 0.5 * force[a] : 0.0;
+        if (kind == 0)
+            total += j[0];
+        else {
+            double e = 0.0;
+            for (int a = 0; a < L.d; ++a) e += j[a] * j[a];
+            total += 0.5 * e / r;
+        }
+    }
+    return total;
 }

@@ -29,6 +29,9 @@ MUTANTS = {
     "bounce_back_same_direction": ("nxt[opp[i] * N + n] = post;", "nxt[i * N + n] = post;"),
     "force_half_missing_in_readout": ("(j[a] + (force ? 0.5 * force[a] : 0.0)) / r", "(j[a] + (force ? force[a] : 0.0)) / r"),
     "force_not_divided_by_rho": ("sf[a] = s[a] + F[a] / rho;", "sf[a] = s[a] + F[a];"),
+    "gray_same_direction": ("post = (1.0 - m) * post + m * cur[opp[i] * N + n];",
+                            "post = (1.0 - m) * post + m * cur[i * N + n];"),
+    "kinetic_energy_factor": ("total += 0.5 * e / r;", "total += e / r;"),
 }
 
 
@@ -48,6 +51,7 @@ def test_pins_catch_mutant(mutant):
         env = dict(os.environ, LBM_ORACLE_LIB=so, OMP_NUM_THREADS="2")
         r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                             os.path.join(ROOT, "tests", "test_oracle_pins.py"),
-                            os.path.join(ROOT, "tests", "test_oracle_walls_force.py")], cwd=ROOT, env=env,
+                            os.path.join(ROOT, "tests", "test_oracle_walls_force.py"),
+                            os.path.join(ROOT, "tests", "test_oracle_gray.py")], cwd=ROOT, env=env,
                            capture_output=True, text=True, timeout=600)
         assert r.returncode != 0, f"mutant {mutant} survived the pins:\n{r.stdout[-2000:]}"
