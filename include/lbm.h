@@ -96,11 +96,15 @@ typedef struct lbm_params {
                             0 for D2Q9. */
 } lbm_params;
 
-/* lbm_params.flags bits. */
+/* lbm_params.flags bits (at most one of the two). */
 #define LBM_FLAG_MASK 1 /* a solid mask is passed to lbm_init: cells with mask = 1 are solid and
                            fluid cells see them through halfway bounce-back -- a population
                            leaving x towards a solid x + c_i returns to x as c_opp(i) one step
                            later. Solid cells carry no state (read out as zeros). */
+#define LBM_FLAG_GRAY 2 /* a gray field m in [0, 1] (float per cell) is passed to lbm_init: the
+                           post-collision populations become (1 - m) f^BGK_i + m f_opp(i), a
+                           partial bounce-back on the node that is differentiable in m (m = 1
+                           reflects everything). The library keeps its own copy. */
 
 /* Host-side quantities derived from lbm_params (lbm_prepare). All FP64. */
 typedef struct lbm_derived {
@@ -132,7 +136,7 @@ int lbm_prepare(const lbm_params *p, lbm_derived *out);
 int64_t lbm_pop_bytes(const lbm_params *p);
 
 /* Bytes of device scratch lbm_init needs (reduction partials, plus 4 bytes per cell of link
- * words when LBM_FLAG_MASK is set). -1 if p is invalid. */
+ * words or gray fractions when LBM_FLAG_MASK or LBM_FLAG_GRAY is set). -1 if p is invalid. */
 int64_t lbm_scratch_bytes(const lbm_params *p);
 
 /* Create a context and write the initial state f_i(0, x) = f^eq_i(rho0(x), s0(x)).
@@ -141,12 +145,13 @@ int64_t lbm_scratch_bytes(const lbm_params *p);
  *   scratch:      device buffer of lbm_scratch_bytes(p), 256-byte aligned.
  *   rho0:         device FP64 [N] initial density (read during this call's device work).
  *   s0:           device FP64 [d][N] initial lattice velocity.
- *   mask:         device uint8 [N], 1 = solid (read during this call's device work), required
- *                 when p->flags has LBM_FLAG_MASK and NULL otherwise.
+ *   mask:         with LBM_FLAG_MASK: device uint8 [N], 1 = solid; with LBM_FLAG_GRAY: device
+ *                 float [N], the gray fraction in [0, 1]; NULL otherwise. Read during this
+ *                 call's device work only.
  *   stream:       hipStream_t for all work of this context.
  * On success *out receives the context (free with lbm_destroy). Asynchronous. */
 int lbm_init(lbm_ctx **out, const lbm_params *p, void *pop_a, void *pop_b, void *scratch, const double *rho0,
-             const double *s0, const uint8_t *mask, void *stream);
+             const double *s0, const void *mask, void *stream);
 
 /* Advance by nsteps >= 0 steps of eq:LBE_BGK: one fused kernel per step that gathers the
  * streamed populations, forms rho and s, builds f^eq_i and relaxes with 1/tau.
@@ -186,14 +191,41 @@ int64_t lbm_time(const lbm_ctx *ctx);
  * the same arithmetic whatever work-group computes it. */
 int lbm_set_launch(lbm_ctx *ctx, int32_t block_x, int32_t block_y, int32_t flags);
 
-/* Gradient of an objective with respect to the tensor entries, tau and a per-cell mask.
- * Not implemented by this build: always returns LBM_ERR_UNSUPPORTED. */
+/* Gradients by the discrete adjoint of the step (reverse sweep with checkpointing).
+ *
+ * lbm_grad advances the context by spec->nsteps steps (exactly as lbm_step would), evaluates
+ * the objective J on the final state and returns the derivatives of J with respect to the
+ * tensor entries, tau and the per-cell gray fraction, the state at the start of the call
+ * being held fixed. Objectives (all sums in FP64):
+ *   0  mass flux through the plane x = outlet_plane:  J = sum over its cells of (j_x + F_x/2)
+ *   1  kinetic energy:                                J = sum over cells of |j + F/2|^2 / (2 rho)
+ * with j = sum_i f_i c_i. The forward states are kept every checkpoint_every steps and each
+ * segment is recomputed (bit-identically) before its reverse steps. The adjoint populations
+ * use the arithmetic precision of the storage; the parameter sums are FP64.
+ * Supported: LBM_TENSOR_THETA and LBM_TENSOR_A, no mask or LBM_FLAG_GRAY (binary masks and
+ * LBM_TENSOR_ATILDE return LBM_ERR_UNSUPPORTED). */
 typedef struct lbm_grad_spec {
-    int32_t objective; /* 0 = outlet mass flux, 1 = kinetic energy */
-    int32_t reserved;
-    int64_t nsteps, checkpoint_every, outlet_plane;
+    int32_t objective;        /* 0 = outlet mass flux, 1 = kinetic energy                    */
+    int32_t reserved;         /* must be 0                                                   */
+    int64_t nsteps;           /* steps of the forward pass, >= 0                              */
+    int64_t checkpoint_every; /* steps per recomputed segment, >= 1                           */
+    int64_t outlet_plane;     /* x index of the flux plane (objective 0), 0 <= . < nx         */
 } lbm_grad_spec;
-int lbm_grad(lbm_ctx *ctx, const lbm_grad_spec *spec, double *dtensor, double *dtau, double *dmask);
+
+/* Device workspace lbm_grad needs for this context and spec (checkpoints, one segment of
+ * recomputed states, two adjoint buffers, partial sums); a negative LBM_ERR_* code when the
+ * request is invalid or unsupported. */
+int64_t lbm_grad_workspace_bytes(const lbm_ctx *ctx, const lbm_grad_spec *spec);
+
+/*   workspace: device buffer of lbm_grad_workspace_bytes, 256-byte aligned.
+ *   objective: host out, J.
+ *   dtensor:   host out [9] (may be NULL): dJ/dT_ab for the tensor as given, one value per
+ *              independent entry (T_ab and T_ba are one entry), written symmetrically.
+ *   dtau:      host out (may be NULL): dJ/dtau.
+ *   dmask:     device out FP64 [N] (may be NULL): dJ/dm per cell (zeros without a gray field).
+ * Synchronises the stream before returning. */
+int lbm_grad(lbm_ctx *ctx, const lbm_grad_spec *spec, void *workspace, double *objective, double *dtensor,
+             double *dtau, double *dmask);
 
 /* Free a context (NULL is allowed). Does not touch the caller's buffers. */
 void lbm_destroy(lbm_ctx *ctx);

@@ -32,6 +32,7 @@ LBM_TENSOR_THETA, LBM_TENSOR_A, LBM_TENSOR_ATILDE = 0, 1, 2
 LBM_SHIFT_REST, LBM_SHIFT_WEIGHT = 0, 1
 LBM_LAUNCH_XCD_SLABS = 1
 LBM_FLAG_MASK = 1
+LBM_FLAG_GRAY = 2
 
 LATTICES = {"D2Q9": LBM_D2Q9, "D3Q19": LBM_D3Q19, "D3Q27": LBM_D3Q27}
 STORAGES = {"f64": LBM_F64, "f32": LBM_F32, "f16": LBM_F16, "bf16": LBM_BF16}
@@ -57,6 +58,9 @@ class lbm_derived(ctypes.Structure):
 class lbm_grad_spec(ctypes.Structure):
     _fields_ = [("objective", ctypes.c_int32), ("reserved", ctypes.c_int32), ("nsteps", ctypes.c_int64),
                 ("checkpoint_every", ctypes.c_int64), ("outlet_plane", ctypes.c_int64)]
+
+
+OBJECTIVES = {"flux": 0, "kinetic_energy": 1}
 
 
 class LBMError(RuntimeError):
@@ -90,7 +94,8 @@ def _bind(path: str):
         "lbm_get_f64": (ctypes.c_int, [vp, vp]),
         "lbm_time": (i64, [vp]),
         "lbm_set_launch": (ctypes.c_int, [vp, i32, i32, i32]),
-        "lbm_grad": (ctypes.c_int, [vp, ctypes.POINTER(lbm_grad_spec), dp, dp, vp]),
+        "lbm_grad_workspace_bytes": (i64, [vp, ctypes.POINTER(lbm_grad_spec)]),
+        "lbm_grad": (ctypes.c_int, [vp, ctypes.POINTER(lbm_grad_spec), vp, dp, dp, dp, vp]),
         "lbm_destroy": (None, [vp]),
         "lbm_last_error": (ctypes.c_char_p, []),
         "lbm_stream_copy": (ctypes.c_int, [vp, vp, i64, vp]),
@@ -138,14 +143,14 @@ def lbm_lattice_info(lattice: int):
 
 
 def make_params(lattice="D3Q19", storage="f32", shape=(1, 1, 1), tensor=None, tensor_kind="theta", tau=0.8,
-                order=3, rho0=1.0, shift="rest", force=None, masked=False) -> lbm_params:
+                order=3, rho0=1.0, shift="rest", force=None, masked=False, gray=False) -> lbm_params:
     p = lbm_params()
     p.lattice = LATTICES[lattice] if isinstance(lattice, str) else int(lattice)
     p.storage = STORAGES[storage] if isinstance(storage, str) else int(storage)
     p.order = int(order)
     p.tensor_kind = TENSOR_KINDS[tensor_kind] if isinstance(tensor_kind, str) else int(tensor_kind)
     p.shift_kind = SHIFTS[shift] if isinstance(shift, str) else int(shift)
-    p.flags = LBM_FLAG_MASK if masked else 0
+    p.flags = (LBM_FLAG_MASK if masked else 0) | (LBM_FLAG_GRAY if gray else 0)
     nx, ny, nz = (tuple(shape) + (1, 1, 1))[:3]
     p.nx, p.ny, p.nz = int(nx), int(ny), int(nz)
     t = [1.0 / 3.0, 0, 0, 0, 1.0 / 3.0, 0, 0, 0, 1.0 / 3.0] if tensor is None else [float(v) for v in
@@ -226,10 +231,32 @@ def lbm_set_launch(ctx: int, block_x: int, block_y: int, flags: int = 0) -> None
     _check(_lib.lbm_set_launch(ctx, int(block_x), int(block_y), int(flags)))
 
 
-def lbm_grad(ctx: int, spec: lbm_grad_spec, dtensor=None, dtau=None, dmask=None) -> None:
+def make_grad_spec(objective="kinetic_energy", nsteps=0, checkpoint_every=100, outlet_plane=0) -> lbm_grad_spec:
+    spec = lbm_grad_spec()
+    spec.objective = OBJECTIVES[objective] if isinstance(objective, str) else int(objective)
+    spec.reserved = 0
+    spec.nsteps = int(nsteps)
+    spec.checkpoint_every = int(checkpoint_every)
+    spec.outlet_plane = int(outlet_plane)
+    return spec
+
+
+def lbm_grad_workspace_bytes(ctx: int, spec: lbm_grad_spec) -> int:
+    n = _lib.lbm_grad_workspace_bytes(ctx, ctypes.byref(spec))
+    if n < 0:
+        raise LBMError(int(n), lbm_last_error())
+    return n
+
+
+def lbm_grad(ctx: int, spec: lbm_grad_spec, workspace, dmask=None):
+    """Returns (J, dtensor as a 3 x 3 nested list, dtau); dmask (device FP64 [N]) is filled in
+    place when given."""
+    obj = ctypes.c_double()
     dt = (ctypes.c_double * 9)()
     du = ctypes.c_double()
-    _check(_lib.lbm_grad(ctx, ctypes.byref(spec), dt, ctypes.byref(du), _ptr(dmask)))
+    _check(_lib.lbm_grad(ctx, ctypes.byref(spec), _ptr(workspace), ctypes.byref(obj), dt, ctypes.byref(du),
+                         _ptr(dmask)))
+    return obj.value, [list(dt[3 * a: 3 * a + 3]) for a in range(3)], du.value
 
 
 def lbm_destroy(ctx: int) -> None:
@@ -268,7 +295,8 @@ class Simulation:
         s_t = torch.as_tensor(s, dtype=torch.float64).reshape(self.d, self.n).to(self.device).contiguous()
         mask_t = None
         if mask is not None:
-            mask_t = torch.as_tensor(mask).reshape(self.n).to(torch.uint8).to(self.device).contiguous()
+            mtype = torch.float32 if params.flags & LBM_FLAG_GRAY else torch.uint8
+            mask_t = torch.as_tensor(mask).reshape(self.n).to(mtype).to(self.device).contiguous()
         torch.cuda.synchronize(self.device)
         self.ctx = lbm_init(params, self.pop_a, self.pop_b, self.scratch, rho_t, s_t, mask_t,
                             self.stream.cuda_stream)
@@ -318,3 +346,49 @@ class Simulation:
 
     def set_populations(self, buf):
         lbm_set_populations(self.ctx, buf)
+
+    def grad(self, objective="kinetic_energy", nsteps=0, checkpoint_every=100, outlet_plane=0, want_dmask=True):
+        """Advance nsteps and return (J, dJ/dtensor [3 x 3], dJ/dtau, dJ/dm [N] device tensor or None)
+        by the adjoint (see lbm_grad); the workspace is allocated with torch for this call."""
+        torch = self.torch
+        spec = make_grad_spec(objective, nsteps, checkpoint_every, outlet_plane)
+        ws = torch.empty(lbm_grad_workspace_bytes(self.ctx, spec), dtype=torch.uint8, device=self.device)
+        dmask = torch.empty(self.n, dtype=torch.float64, device=self.device) if want_dmask else None
+        j, dt, du = lbm_grad(self.ctx, spec, ws, dmask)
+        return j, dt, du, dmask
+
+
+class Objective:
+    """torch.autograd.Function factory: J(tensor, tau, gray) of a fixed workload, with the
+    gradients from one lbm_grad call (the forward computes them; backward scales them)."""
+
+    @staticmethod
+    def function():
+        import torch
+
+        class _Fn(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, tensor, tau, gray, cfg):
+                p = make_params(cfg["lattice"], cfg["storage"], cfg["shape"], tensor.detach().cpu().numpy(),
+                                cfg.get("tensor_kind", "theta"), float(tau), cfg.get("order", 3),
+                                force=cfg.get("force"), gray=gray is not None)
+                sim = Simulation(p, cfg["rho"], cfg["s"], mask=None if gray is None else gray.detach())
+                j, dt, du, dm = sim.grad(cfg.get("objective", "kinetic_energy"), cfg["nsteps"],
+                                         cfg.get("checkpoint_every", 100), cfg.get("outlet_plane", 0),
+                                         want_dmask=gray is not None)
+                sim.close()
+                ctx.save_for_backward(torch.tensor(dt, dtype=tensor.dtype), torch.tensor(du, dtype=torch.float64),
+                                      dm if dm is not None else torch.zeros(0))
+                ctx.has_gray = gray is not None
+                ctx.gray_dtype = None if gray is None else gray.dtype
+                return torch.tensor(j, dtype=torch.float64)
+
+            @staticmethod
+            def backward(ctx, gout):
+                dt, du, dm = ctx.saved_tensors
+                gt = (gout.cpu() * dt).to(dt.dtype)
+                gu = gout.cpu() * du
+                gg = (gout.to(dm.device) * dm).to(ctx.gray_dtype) if ctx.has_gray else None
+                return gt, gu, gg, None
+
+        return _Fn

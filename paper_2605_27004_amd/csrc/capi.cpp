@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <string>
 
@@ -158,7 +159,9 @@ int prepare(const lbm_params *p, Prepared &out)
         return fail(LBM_ERR_ARG, "unknown tensor kind %d", p->tensor_kind);
     if (p->shift_kind != LBM_SHIFT_REST && p->shift_kind != LBM_SHIFT_WEIGHT)
         return fail(LBM_ERR_ARG, "unknown shift kind %d", p->shift_kind);
-    if (p->flags & ~LBM_FLAG_MASK) return fail(LBM_ERR_ARG, "unknown flags 0x%x", p->flags);
+    if (p->flags & ~(LBM_FLAG_MASK | LBM_FLAG_GRAY)) return fail(LBM_ERR_ARG, "unknown flags 0x%x", p->flags);
+    if ((p->flags & LBM_FLAG_MASK) && (p->flags & LBM_FLAG_GRAY))
+        return fail(LBM_ERR_ARG, "LBM_FLAG_MASK and LBM_FLAG_GRAY are exclusive");
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(p->force[a])) return fail(LBM_ERR_ARG, "force has a non-finite entry");
     if (d == 2 && p->force[2] != 0.0) return fail(LBM_ERR_ARG, "D2Q9 needs force[2] == 0");
@@ -264,8 +267,10 @@ template <typename C> StepConsts<C> consts_for(const lbm_params &p, const Prepar
 // aligned pieces.
 int64_t links_bytes(const lbm_params &p, uint32_t n)
 {
-    return (p.flags & LBM_FLAG_MASK) ? ((int64_t)n * 4 + 255) / 256 * 256 : 0;
+    return (p.flags & (LBM_FLAG_MASK | LBM_FLAG_GRAY)) ? ((int64_t)n * 4 + 255) / 256 * 256 : 0;
 }
+
+int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
 
 bool aligned256(const void *ptr) { return ((uintptr_t)ptr & 255u) == 0; }
 
@@ -281,6 +286,7 @@ struct lbm_ctx {
     int cur;
     double *partials;
     uint32_t *links;  // null without a solid mask
+    float *gray;      // null without a gray field
     hipStream_t stream;
     int64_t t;
     int block_x, block_y;
@@ -331,7 +337,7 @@ int64_t lbm_scratch_bytes(const lbm_params *p)
 }
 
 int lbm_init(lbm_ctx **out, const lbm_params *p, void *pop_a, void *pop_b, void *scratch, const double *rho0,
-             const double *s0, const uint8_t *mask, void *stream)
+             const double *s0, const void *mask, void *stream)
 {
     if (!out) return fail(LBM_ERR_ARG, "out is NULL");
     *out = nullptr;
@@ -339,8 +345,9 @@ int lbm_init(lbm_ctx **out, const lbm_params *p, void *pop_a, void *pop_b, void 
     int rc = prepare(p, pr);
     if (rc) return rc;
     const bool masked = p->flags & LBM_FLAG_MASK;
-    if (masked && !mask) return fail(LBM_ERR_ARG, "LBM_FLAG_MASK is set but mask is NULL");
-    if (!masked && mask) return fail(LBM_ERR_ARG, "a mask was passed without LBM_FLAG_MASK");
+    const bool grayed = p->flags & LBM_FLAG_GRAY;
+    if ((masked || grayed) && !mask) return fail(LBM_ERR_ARG, "LBM_FLAG_MASK / LBM_FLAG_GRAY is set but mask is NULL");
+    if (!masked && !grayed && mask) return fail(LBM_ERR_ARG, "a mask was passed without LBM_FLAG_MASK / LBM_FLAG_GRAY");
     if (!pop_a || !pop_b || !scratch || !rho0 || !s0) return fail(LBM_ERR_ARG, "a device pointer is NULL");
     if (pop_a == pop_b) return fail(LBM_ERR_ARG, "pop_a and pop_b must be distinct buffers");
     if (!aligned256(pop_a) || !aligned256(pop_b) || !aligned256(scratch))
@@ -356,6 +363,7 @@ int lbm_init(lbm_ctx **out, const lbm_params *p, void *pop_a, void *pop_b, void 
     c->pop[1] = pop_b;
     c->cur = 0;
     c->links = masked ? (uint32_t *)scratch : nullptr;
+    c->gray = grayed ? (float *)scratch : nullptr;
     c->partials = (double *)((char *)scratch + links_bytes(*p, pr.n));
     c->stream = (hipStream_t)stream;
     c->t = 0;
@@ -366,7 +374,8 @@ int lbm_init(lbm_ctx **out, const lbm_params *p, void *pop_a, void *pop_b, void 
     c->block_y = 256 / c->block_x;
     c->launch_flags = 0;
     hipError_t e = hipSuccess;
-    if (masked) e = launch_links(p->lattice, c->grid, mask, c->links, c->stream);
+    if (masked) e = launch_links(p->lattice, c->grid, (const uint8_t *)mask, c->links, c->stream);
+    if (grayed) e = hipMemcpyAsync(c->gray, mask, (size_t)pr.n * 4, hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess)
         e = launch_init(p->lattice, p->storage, p->order, c->grid, c->k64, rho0, s0, c->links, c->pop[0], c->stream);
     if (e != hipSuccess) {
@@ -383,8 +392,8 @@ int lbm_step(lbm_ctx *c, int64_t nsteps)
     if (nsteps < 0) return fail(LBM_ERR_ARG, "nsteps must be >= 0");
     for (int64_t s = 0; s < nsteps; ++s) {
         hipError_t e = launch_step(c->p.lattice, c->p.storage, c->p.order, c->grid, c->k64, c->k32, c->links,
-                                   c->pop[c->cur], c->pop[c->cur ^ 1], c->block_x, c->block_y, c->launch_flags,
-                                   c->stream);
+                                   c->gray, c->pop[c->cur], c->pop[c->cur ^ 1], c->block_x, c->block_y,
+                                   c->launch_flags, c->stream);
         if (e != hipSuccess) return fail_hip(e, "step kernel launch");
         c->cur ^= 1;
         ++c->t;
@@ -456,14 +465,144 @@ int lbm_set_launch(lbm_ctx *c, int32_t block_x, int32_t block_y, int32_t flags)
     return LBM_OK;
 }
 
-int lbm_grad(lbm_ctx *c, const lbm_grad_spec *spec, double *dtensor, double *dtau, double *dmask)
+namespace {
+
+struct GradLayout {
+    int64_t nseg, seglen;
+    int64_t ckpt, seg, lam_a, lam_b, gpart, jpart, sums, total;  // byte offsets / size
+};
+
+int grad_layout(const lbm_ctx *c, const lbm_grad_spec *spec, GradLayout &l)
 {
-    (void)c;
-    (void)spec;
-    (void)dtensor;
-    (void)dtau;
-    (void)dmask;
-    return fail(LBM_ERR_UNSUPPORTED, "lbm_grad is not implemented by this build");
+    if (!c || !spec) return fail(LBM_ERR_ARG, "NULL argument");
+    if (spec->reserved != 0) return fail(LBM_ERR_ARG, "spec->reserved must be 0");
+    if (spec->objective != 0 && spec->objective != 1) return fail(LBM_ERR_ARG, "objective must be 0 or 1");
+    if (spec->nsteps < 0 || spec->checkpoint_every < 1)
+        return fail(LBM_ERR_ARG, "need nsteps >= 0 and checkpoint_every >= 1");
+    if (spec->objective == 0 && (spec->outlet_plane < 0 || spec->outlet_plane >= c->p.nx))
+        return fail(LBM_ERR_ARG, "outlet_plane %lld outside 0..%lld", (long long)spec->outlet_plane,
+                    (long long)(c->p.nx - 1));
+    if (c->links) return fail(LBM_ERR_UNSUPPORTED, "gradients with a binary solid mask are not supported");
+    if (c->p.tensor_kind == LBM_TENSOR_ATILDE)
+        return fail(LBM_ERR_UNSUPPORTED, "gradients for LBM_TENSOR_ATILDE are not supported");
+    const int64_t popb = (int64_t)c->pr.q * c->grid.n * c->pr.bytes;
+    const int64_t lamb = (int64_t)c->pr.q * c->grid.n * (c->p.storage == LBM_F64 ? 8 : 4);
+    const int64_t nb = moments_blocks(c->grid);
+    l.seglen = std::min<int64_t>(spec->checkpoint_every, std::max<int64_t>(spec->nsteps, 1));
+    l.nseg = (spec->nsteps + spec->checkpoint_every - 1) / spec->checkpoint_every;
+    int64_t off = 0;
+    l.ckpt = off;
+    off += align256(popb) * l.nseg;
+    l.seg = off;
+    off += align256(popb) * (l.seglen - 1);
+    l.lam_a = off;
+    off += align256(lamb);
+    l.lam_b = off;
+    off += align256(lamb);
+    l.gpart = off;
+    off += align256(8 * kGradPartialsHost * nb);
+    l.jpart = off;
+    off += align256(8 * nb);
+    l.sums = off;
+    off += 256;
+    l.total = off;
+    return LBM_OK;
+}
+
+}  // namespace
+
+int64_t lbm_grad_workspace_bytes(const lbm_ctx *c, const lbm_grad_spec *spec)
+{
+    GradLayout l;
+    const int rc = grad_layout(c, spec, l);
+    return rc ? rc : l.total;
+}
+
+int lbm_grad(lbm_ctx *c, const lbm_grad_spec *spec, void *workspace, double *objective, double *dtensor,
+             double *dtau, double *dmask)
+{
+    GradLayout l;
+    int rc = grad_layout(c, spec, l);
+    if (rc) return rc;
+    if (!workspace || !objective) return fail(LBM_ERR_ARG, "workspace and objective must not be NULL");
+    if (!aligned256(workspace)) return fail(LBM_ERR_ALIGN, "workspace must be 256-byte aligned");
+    char *ws = (char *)workspace;
+    const int64_t popb = (int64_t)c->pr.q * c->grid.n * c->pr.bytes;
+    const int64_t pstride = align256(popb);
+    const uint32_t nb = moments_blocks(c->grid);
+    hipStream_t st = c->stream;
+    hipError_t e = hipSuccess;
+    auto ckpt = [&](int64_t s) { return (void *)(ws + l.ckpt + s * pstride); };
+    auto segst = [&](int64_t t) { return (void *)(ws + l.seg + (t - 1) * pstride); };  // t >= 1
+
+    // forward pass, keeping the state at the start of every segment
+    for (int64_t sgi = 0; sgi < l.nseg; ++sgi) {
+        e = hipMemcpyAsync(ckpt(sgi), c->pop[c->cur], popb, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return fail_hip(e, "checkpoint copy");
+        const int64_t len = std::min(spec->checkpoint_every, spec->nsteps - sgi * spec->checkpoint_every);
+        rc = lbm_step(c, len);
+        if (rc) return rc;
+    }
+    // seed the reverse sweep with dJ/df at the final state
+    void *lam_in = ws + l.lam_a, *lam_out = ws + l.lam_b;
+    double *gpart = (double *)(ws + l.gpart), *jpart = (double *)(ws + l.jpart), *sums = (double *)(ws + l.sums);
+    e = launch_seed(c->p.lattice, c->p.storage, c->grid, c->k64, c->k32, c->pop[c->cur], lam_in, jpart,
+                    spec->objective, (int)spec->outlet_plane, st);
+    if (e == hipSuccess) e = launch_sum(jpart, nb, 1, sums, st);
+    if (e == hipSuccess) e = launch_zero(gpart, (uint64_t)kGradPartialsHost * nb, st);
+    if (e == hipSuccess && dmask) e = launch_zero(dmask, c->grid.n, st);
+    if (e != hipSuccess) return fail_hip(e, "reverse-sweep set-up");
+    // reverse sweep, one recomputed segment at a time
+    for (int64_t sgi = l.nseg - 1; sgi >= 0; --sgi) {
+        const int64_t len = std::min(spec->checkpoint_every, spec->nsteps - sgi * spec->checkpoint_every);
+        auto state = [&](int64_t t) { return t == 0 ? ckpt(sgi) : segst(t); };
+        for (int64_t t = 1; t < len; ++t) {
+            e = launch_step(c->p.lattice, c->p.storage, c->p.order, c->grid, c->k64, c->k32, nullptr, c->gray,
+                            state(t - 1), state(t), c->block_x, c->block_y, c->launch_flags, st);
+            if (e != hipSuccess) return fail_hip(e, "segment recompute");
+        }
+        for (int64_t t = len - 1; t >= 0; --t) {
+            e = launch_adjoint(c->p.lattice, c->p.storage, c->p.order, c->grid, c->k64, c->k32, state(t), lam_in,
+                               lam_out, c->gray, dmask, gpart, st);
+            if (e != hipSuccess) return fail_hip(e, "adjoint step");
+            std::swap(lam_in, lam_out);
+        }
+    }
+    e = launch_sum(gpart, nb, kGradPartialsHost, sums + 1, st);
+    double h[1 + kGradPartialsHost];
+    if (e == hipSuccess) e = hipMemcpyAsync(h, sums, sizeof h, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail_hip(e, "gradient read-back");
+    *objective = h[0];
+    if (dtau) *dtau = h[10];
+    if (dtensor) {
+        const int d = c->pr.d;
+        double G[9];  // dJ/dK as a general matrix
+        for (int i = 0; i < 9; ++i) G[i] = h[1 + i];
+        double D[9] = {0};  // dJ/dT as a general matrix
+        if (c->p.tensor_kind == LBM_TENSOR_THETA) {
+            for (int i = 0; i < 9; ++i) D[i] = G[i] / kCs2;  // K = T / cs^2 - I
+        } else {  // T = A, K = A^-1 - I: dJ/dA = -A^-1 G A^-1
+            const double *ai = c->pr.dv.ainv;
+            double t[9] = {0};
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b)
+                    for (int k2 = 0; k2 < 3; ++k2) t[a * 3 + b] += ai[a * 3 + k2] * G[k2 * 3 + b];
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b) {
+                    double v = 0.0;
+                    for (int k2 = 0; k2 < 3; ++k2) v += t[a * 3 + k2] * ai[k2 * 3 + b];
+                    D[a * 3 + b] = -v;
+                }
+        }
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double v = 0.0;
+                if (a < d && b < d) v = (a == b) ? D[a * 3 + a] : D[a * 3 + b] + D[b * 3 + a];
+                dtensor[a * 3 + b] = v;
+            }
+    }
+    return LBM_OK;
 }
 
 void lbm_destroy(lbm_ctx *c) { delete c; }

@@ -53,9 +53,22 @@ hipError_t launch_init(int lattice, int storage, int order, const Grid &g, const
 // Launch flags of the step kernel (same values as LBM_LAUNCH_* in lbm.h).
 constexpr int kLaunchXcdSlabs = 1;  // XCD-contiguous tile order
 
+// gray: per-cell gray fraction m (partial bounce-back) or null.
 hipError_t launch_step(int lattice, int storage, int order, const Grid &g, const StepConsts<double> &k64,
-                       const StepConsts<float> &k32, const uint32_t *links, const void *src, void *dst, int block_x,
-                       int block_y, int flags, hipStream_t stream);
+                       const StepConsts<float> &k32, const uint32_t *links, const float *gray, const void *src,
+                       void *dst, int block_x, int block_y, int flags, hipStream_t stream);
+
+// ---- the gradient path (reverse sweep) ----
+constexpr int kGradPartialsHost = 10;  // per work-group: dJ/dK (9, general matrix), dJ/dtau
+// lam: adjoint populations [q][N] in the arithmetic precision of the storage.
+hipError_t launch_seed(int lattice, int storage, const Grid &g, const StepConsts<double> &k64,
+                       const StepConsts<float> &k32, const void *src, void *lam, double *jpart, int kind, int plane,
+                       hipStream_t stream);
+hipError_t launch_adjoint(int lattice, int storage, int order, const Grid &g, const StepConsts<double> &k64,
+                          const StepConsts<float> &k32, const void *state, const void *lam_in, void *lam_out,
+                          const float *gray, double *dmask, double *gpart, hipStream_t stream);
+hipError_t launch_sum(const double *part, uint32_t nblocks, int m, double *out, hipStream_t stream);
+hipError_t launch_zero(double *p, uint64_t n, hipStream_t stream);
 
 // rho / s may be null. partials: scratch of kPartials * nblocks doubles; totals: kPartials
 // doubles of scratch (sum drho, sum rho s_x, _y, _z, fluid cells).

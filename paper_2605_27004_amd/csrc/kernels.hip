@@ -316,14 +316,18 @@ template <int LAT> __device__ inline Slot slot_minus(const Cell &c, int p, uint3
     return Slot{2 * p + 2, src_minus<LAT>(c, p)};
 }
 
-// Plain periodic fluid (GENERAL = false): 19 pulls, collision, 19 streaming stores per cell.
-// GENERAL = true adds the link word of each cell (solid cells return at once, links to solid
-// cells bounce back) and the body force.
-template <int LAT, typename S, int ORDER, bool GENERAL>
+// Step variants: kPlain (periodic fluid: q pulls, collision, q streaming stores per cell);
+// kLinks (link word per cell: solid cells write zeros, links to solid cells bounce back, plus
+// the body force); kGray (gray fraction m per cell: f* = (1 - m) f^BGK + m f_opp, plus the
+// body force).
+enum StepMode : int { kPlain = 0, kLinks = 1, kGray = 2 };
+
+template <int LAT, typename S, int ORDER, int MODE>
 __global__ __launch_bounds__(256) void k_step(const S *__restrict__ src, S *__restrict__ dst, const Grid g,
                                               const StepConsts<typename Conv<S>::C> k, const TileMap m,
-                                              const uint32_t *__restrict__ links)
+                                              const uint32_t *__restrict__ links, const float *__restrict__ gray)
 {
+    constexpr bool GENERAL = MODE == kLinks;
     using L = Lattice<LAT>;
     using C = typename Conv<S>::C;
     constexpr int NP = L::NP;
@@ -363,7 +367,25 @@ __global__ __launch_bounds__(256) void k_step(const S *__restrict__ src, S *__re
         }
     }
 
-    if constexpr (!GENERAL) collide_cell<LAT, ORDER, false, C>(k, gp, gm);
+    if constexpr (MODE == kPlain) collide_cell<LAT, ORDER, false, C>(k, gp, gm);
+    if constexpr (MODE == kGray) {
+        C pp[NP + 1], pm[NP + 1];
+#pragma unroll
+        for (int p = 0; p <= NP; ++p) {
+            pp[p] = gp[p];
+            pm[p] = gm[p];
+        }
+        collide_cell<LAT, ORDER, true, C>(k, gp, gm);
+        // partial bounce-back on the node: the opposite of +c is -c of the same pair
+        const C mg = (C)gray[c.own];
+        gp[0] = fmad(mg, pp[0] - gp[0], gp[0]);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const C a = gp[p + 1];
+            gp[p + 1] = fmad(mg, pm[p + 1] - a, a);
+            gm[p + 1] = fmad(mg, pp[p + 1] - gm[p + 1], gm[p + 1]);
+        }
+    }
     st_stream(plane(dst, 0, g.n), c.own, Conv<S>::st(gp[0]));
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
@@ -551,6 +573,332 @@ __global__ __launch_bounds__(256) void k_copy(const u32x4 *__restrict__ src, u32
     if (i < n) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
+// ---- the discrete adjoint ----------------------------------------------------------------------
+//
+// One forward step maps the pre-collision state f(t) to f(t+1) by
+//   b_k  = (1 - w) f_k + w f^eq_k(rho, s) + [f^eq_k(rho, s') - f^eq_k(rho, s)]   (force: s' = s + F/rho)
+//   f*_k = (1 - m) b_k + m f_opp(k)                                                 (gray cells)
+//   f_k(t+1, x + c_k) = f*_k(x)
+// with w = 1/tau. Its transpose takes the adjoint lam(t+1) of f(t+1) to lam(t):
+//   mu_k(x) = lam_k(t+1, x + c_k),  nu_k = (1 - m) mu_k,
+//   lam_i(t, x) = (1 - w) nu_i + a VJP_s(nu)_i + [VJP_s'(nu)_i] + m mu_opp(i),
+// a = w without force and w - 1 with it, and VJP_s(nu)_i = sum_k nu_k d f^eq_k / d f_i =
+// A0 + sum_a A_a (c_ia - s_a) / rho through rho = sum f and s = sum f c / rho. Parameter
+// sensitivities accumulate per cell: d tau += -w^2 sum_k nu_k (f^eq_k - f_k),
+// d K += a G_s(nu) [+ G_s'(nu)], d m += sum_k mu_k (f_opp(k) - b_k). All formulas are in terms
+// of f; the stored deviations differ from f by constants, which cancel in every difference.
+
+// A0, A_a and the K-sensitivity G (9 entries, K treated as a general matrix; add coef * G)
+// of sum_k nu_k f^eq_k(rho, s) for f^eq_k = rho r_k + w_k rho P'_k(s).
+template <int LAT, int ORDER, typename C>
+__device__ inline void equilibrium_vjp(const StepConsts<C> &k, C rho, C sx, C sy, C sz, const C *nup, const C *num,
+                                       C &A0, C &Ax, C &Ay, C &Az, C coef, C *G)
+{
+    using L = Lattice<LAT>;
+    const C usq = fmad(sx, sx, fmad(sy, sy, sz * sz));
+    const C ksx = fmad(k.k[0], sx, fmad(k.k[3], sy, k.k[4] * sz));
+    const C ksy = fmad(k.k[3], sx, fmad(k.k[1], sy, k.k[5] * sz));
+    const C ksz = fmad(k.k[4], sx, fmad(k.k[5], sy, k.k[2] * sz));
+    const C even0 = C(-1.5) * usq;
+    const C bq = C(-4.5) * usq;
+    // rest velocity: u = 0, P' = -1.5 |s|^2, dP'/ds = -3 s
+    const C phi0 = nup[0] * k.w[0];
+    A0 = nup[0] * fmad(k.w[0], even0, k.rest[0]);
+    C S1[3] = {C(0), C(0), C(0)}, S3[3] = {C(0), C(0), C(0)};
+    C S2 = C(3) * phi0;
+    C T0 = phi0, U0 = C(0);
+    C T[6] = {C(0), C(0), C(0), C(0), C(0), C(0)}, U[6] = {C(0), C(0), C(0), C(0), C(0), C(0)};  // xx yy zz xy xz yz
+#pragma unroll
+    for (int p = 0; p < L::NP; ++p) {
+        const PairRow v = L::pair(p);
+        C u = C(0), kc = C(0);
+        if (v.cx > 0) { u += sx; kc += ksx; }
+        if (v.cx < 0) { u -= sx; kc -= ksx; }
+        if (v.cy > 0) { u += sy; kc += ksy; }
+        if (v.cy < 0) { u -= sy; kc -= ksy; }
+        if (v.cz > 0) { u += sz; kc += ksz; }
+        if (v.cz < 0) { u -= sz; kc -= ksz; }
+        const C u2 = u * u;
+        const C even = fmad(C(4.5), u2, even0);
+        C odd, Bp, Bm;
+        if constexpr (ORDER == 3) {
+            odd = fmad(u, fmad(C(4.5), u2, k.a[p + 1] + bq), C(-3) * kc);
+            // dP'/ds_a = c_a B - (3 + 9u) s_a - 3 (K c)_a with B = A + 9u - 4.5 |s|^2 + 13.5 u^2
+            // (A = k.a already holds the constant 3 of the linear term)
+            const C be = fmad(C(13.5), u2, k.a[p + 1] + bq);
+            Bp = fmad(C(9), u, be);
+            Bm = fmad(C(-9), u, be);
+        } else {
+            odd = C(3) * u;
+            Bp = fmad(C(9), u, C(3));
+            Bm = fmad(C(-9), u, C(3));
+        }
+        const C w = k.w[p + 1];
+        const C np_ = nup[p + 1], nm_ = num[p + 1];
+        const C fp = np_ * w, fm = nm_ * w;
+        A0 = fmad(np_, fmad(w, even + odd, k.rest[p + 1]), A0);
+        A0 = fmad(nm_, fmad(w, even - odd, k.rest[p + 1]), A0);
+        const C sum = fp + fm, dif = fp - fm;
+        const C sB = fp * Bp - fm * Bm;  // sum_k phi_k B_k c_k along c
+        if constexpr (ORDER == 3)
+            S2 = fmad(C(9) * u, dif, fmad(C(3), sum, S2));
+        else
+            S2 = fmad(C(3), sum, S2);
+        T0 += sum;
+        U0 = fmad(u, dif, U0);
+        const C ud = u * dif;
+        const int cv[3] = {v.cx, v.cy, v.cz};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (cv[a] > 0) { S1[a] += sB; S3[a] += dif; }
+            if (cv[a] < 0) { S1[a] -= sB; S3[a] -= dif; }
+        }
+        // c_a c_b products are +1, -1 or 0
+        const int cc[6] = {cv[0] * cv[0], cv[1] * cv[1], cv[2] * cv[2], cv[0] * cv[1], cv[0] * cv[2], cv[1] * cv[2]};
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+            if (cc[e] > 0) { T[e] += sum; U[e] += ud; }
+            if (cc[e] < 0) { T[e] -= sum; U[e] -= ud; }
+        }
+    }
+    const C s[3] = {sx, sy, sz};
+    C Aa[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) Aa[a] = S1[a] - s[a] * S2;
+    if constexpr (ORDER == 3) {
+        Aa[0] -= C(3) * fmad(k.k[0], S3[0], fmad(k.k[3], S3[1], k.k[4] * S3[2]));
+        Aa[1] -= C(3) * fmad(k.k[3], S3[0], fmad(k.k[1], S3[1], k.k[5] * S3[2]));
+        Aa[2] -= C(3) * fmad(k.k[4], S3[0], fmad(k.k[5], S3[1], k.k[2] * S3[2]));
+    }
+    Ax = rho * Aa[0];
+    Ay = rho * Aa[1];
+    Az = rho * Aa[2];
+    // G_ab = rho [1.5 T_ab - 0.5 d_ab T0 + 4.5 U_ab - 1.5 d_ab U0 - 3 S3_a s_b] (the U, S3 terms at order 3)
+    const int ie[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+    const C rc = rho * coef;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            C t = C(1.5) * T[ie[a][b]];
+            if (a == b) t -= C(0.5) * T0;
+            if constexpr (ORDER == 3) {
+                t = fmad(C(4.5), U[ie[a][b]], t);
+                if (a == b) t -= C(1.5) * U0;
+                t -= C(3) * S3[a] * s[b];
+            }
+            G[3 * a + b] = fmad(rc, t, G[3 * a + b]);
+        }
+}
+
+constexpr int kGradPartials = 10;  // G (9) and d tau, per work-group
+
+// Seed of the reverse sweep from the final state: lam_i = dJ / d f_i, and the objective's
+// per-work-group partial sums. kind 0: flux through the plane x = plane, J = sum (j_x + F_x/2);
+// kind 1: kinetic energy, J = sum |j + F/2|^2 / (2 rho). (plane_x: the flux plane's x index)
+template <int LAT, typename S>
+__global__ __launch_bounds__(256) void k_seed(const S *__restrict__ src, typename Conv<S>::C *__restrict__ lam,
+                                              double *__restrict__ jpart, const Grid g,
+                                              const StepConsts<typename Conv<S>::C> k, const int kind, const int plane_x)
+{
+    using L = Lattice<LAT>;
+    using C = typename Conv<S>::C;
+    constexpr int NP = L::NP;
+    __shared__ double red[256];
+    const int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int32_t z = blockIdx.z;
+    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    double jv = 0.0;
+    if (x < g.nx && y < g.ny) {
+        const Cell c = cell_of(g, x, y, z);
+        C gp[NP + 1], gm[NP + 1];
+        gp[0] = Conv<S>::ld(ld_at(plane(src, 0, g.n), c.own));
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            gp[p + 1] = Conv<S>::ld(ld_at(plane(src, 2 * p + 1, g.n), src_plus<LAT>(c, p)));
+            gm[p + 1] = Conv<S>::ld(ld_at(plane(src, 2 * p + 2, g.n), src_minus<LAT>(c, p)));
+        }
+        C drho, jx, jy, jz;
+        moments_of<LAT>(gp, gm, drho, jx, jy, jz);
+        const C rho = k.rho0 + drho;
+        const C mx = jx + C(0.5) * k.force[0], my = jy + C(0.5) * k.force[1], mz = jz + C(0.5) * k.force[2];
+        C base = C(0), ux = C(0), uy = C(0), uz = C(0);
+        if (kind == 0) {
+            if (x == plane_x) {
+                ux = C(1);
+                jv = (double)mx;
+            }
+        } else {
+            ux = mx / rho;
+            uy = my / rho;
+            uz = mz / rho;
+            base = C(-0.5) * fmad(ux, ux, fmad(uy, uy, uz * uz));
+            jv = 0.5 * ((double)mx * mx + (double)my * my + (double)mz * mz) / (double)rho;
+        }
+        // lam_i = base + u . c_i
+        st_at(plane(lam, 0, g.n), c.own, base);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const PairRow v = L::pair(p);
+            const C uc = (C)v.cx * ux + (C)v.cy * uy + (C)v.cz * uz;
+            st_at(plane(lam, 2 * p + 1, g.n), c.own, base + uc);
+            st_at(plane(lam, 2 * p + 2, g.n), c.own, base - uc);
+        }
+    }
+    red[tid] = jv;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (tid < h) red[tid] += red[tid + h];
+        __syncthreads();
+    }
+    if (tid == 0) jpart[(blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = red[0];
+}
+
+// One reverse step: lam_in = lam(t+1) (canonical), state = the buffer whose gather gives f(t);
+// writes lam_out = lam(t), adds d m per cell to dmask and the work-group's G / d tau sums to
+// gpart (in the same order every step, so the totals are reproducible).
+template <int LAT, typename S, int ORDER>
+__global__ __launch_bounds__(256) void k_adjoint(const S *__restrict__ state, const typename Conv<S>::C *__restrict__ lam_in,
+                                                 typename Conv<S>::C *__restrict__ lam_out,
+                                                 const float *__restrict__ gray, double *__restrict__ dmask,
+                                                 double *__restrict__ gpart, const Grid g,
+                                                 const StepConsts<typename Conv<S>::C> k)
+{
+    using L = Lattice<LAT>;
+    using C = typename Conv<S>::C;
+    constexpr int NP = L::NP;
+    __shared__ double red[kGradPartials][256];
+    const int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int32_t z = blockIdx.z;
+    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    C G[9] = {C(0), C(0), C(0), C(0), C(0), C(0), C(0), C(0), C(0)};
+    C dtau = C(0);
+    if (x < g.nx && y < g.ny) {
+        const Cell c = cell_of(g, x, y, z);
+        // forward quantities at x
+        C gp[NP + 1], gm[NP + 1];
+        gp[0] = Conv<S>::ld(ld_at(plane(state, 0, g.n), c.own));
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            gp[p + 1] = Conv<S>::ld(ld_at(plane(state, 2 * p + 1, g.n), src_plus<LAT>(c, p)));
+            gm[p + 1] = Conv<S>::ld(ld_at(plane(state, 2 * p + 2, g.n), src_minus<LAT>(c, p)));
+        }
+        C drho, jx, jy, jz;
+        moments_of<LAT>(gp, gm, drho, jx, jy, jz);
+        const C rho = k.rho0 + drho;
+        const C inv = C(1) / rho;
+        const C sx = jx * inv, sy = jy * inv, sz = jz * inv;
+        C eqp[NP + 1], eqm[NP + 1];
+        equilibrium_pairs<LAT, ORDER, C>(k, drho, rho, sx, sy, sz, eqp, eqm);
+        // adjoint of the post-collision populations: mu_k(x) = lam_k(t+1, x + c_k)
+        C mup[NP + 1], mum[NP + 1];
+        mup[0] = ld_at(plane(lam_in, 0, g.n), c.own);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            mup[p + 1] = ld_at(plane(lam_in, 2 * p + 1, g.n), src_minus<LAT>(c, p));
+            mum[p + 1] = ld_at(plane(lam_in, 2 * p + 2, g.n), src_plus<LAT>(c, p));
+        }
+        const C mg = gray ? (C)gray[c.own] : C(0);
+        const C keep = C(1) - mg;
+        C nup[NP + 1], num[NP + 1];
+#pragma unroll
+        for (int p = 0; p <= NP; ++p) {
+            nup[p] = keep * mup[p];
+            num[p] = keep * mum[p];
+        }
+        const C w = k.omega;
+        const C a = k.forced ? w - C(1) : w;
+        C A0, Ax, Ay, Az;
+        equilibrium_vjp<LAT, ORDER, C>(k, rho, sx, sy, sz, nup, num, A0, Ax, Ay, Az, a, G);
+        C base = a * (A0 - (Ax * sx + Ay * sy + Az * sz) * inv);
+        C ax = a * Ax * inv, ay = a * Ay * inv, az = a * Az * inv;
+        // post-BGK values b (deviations) and d tau
+        C bp[NP + 1], bm[NP + 1];
+        bp[0] = fmad(w, eqp[0] - gp[0], gp[0]);
+        dtau = nup[0] * (eqp[0] - gp[0]);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            bp[p + 1] = fmad(w, eqp[p + 1] - gp[p + 1], gp[p + 1]);
+            bm[p + 1] = fmad(w, eqm[p + 1] - gm[p + 1], gm[p + 1]);
+            dtau = fmad(nup[p + 1], eqp[p + 1] - gp[p + 1], dtau);
+            dtau = fmad(num[p + 1], eqm[p + 1] - gm[p + 1], dtau);
+        }
+        dtau *= -w * w;
+        if (k.forced) {
+            const C fjx = jx + k.force[0], fjy = jy + k.force[1], fjz = jz + k.force[2];
+            const C tx = fjx * inv, ty = fjy * inv, tz = fjz * inv;
+            C fqp[NP + 1], fqm[NP + 1];
+            equilibrium_pairs<LAT, ORDER, C>(k, drho, rho, tx, ty, tz, fqp, fqm);
+            bp[0] += fqp[0] - eqp[0];
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                bp[p + 1] += fqp[p + 1] - eqp[p + 1];
+                bm[p + 1] += fqm[p + 1] - eqm[p + 1];
+            }
+            C B0, Bx, By, Bz;
+            equilibrium_vjp<LAT, ORDER, C>(k, rho, tx, ty, tz, nup, num, B0, Bx, By, Bz, C(1), G);
+            base += B0 - (Bx * tx + By * ty + Bz * tz) * inv;
+            ax += Bx * inv;
+            ay += By * inv;
+            az += Bz * inv;
+        }
+        // lam(t) at x and the gray-fraction sensitivity
+        const C om = C(1) - w;
+        C dm = mup[0] * (gp[0] - bp[0]);
+        st_at(plane(lam_out, 0, g.n), c.own, fmad(mg, mup[0], fmad(om, nup[0], base)));
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            const PairRow v = L::pair(p);
+            const C vc = (C)v.cx * ax + (C)v.cy * ay + (C)v.cz * az;
+            st_at(plane(lam_out, 2 * p + 1, g.n), c.own, fmad(mg, mum[p + 1], fmad(om, nup[p + 1], base + vc)));
+            st_at(plane(lam_out, 2 * p + 2, g.n), c.own, fmad(mg, mup[p + 1], fmad(om, num[p + 1], base - vc)));
+            dm = fmad(mup[p + 1], gm[p + 1] - bp[p + 1], dm);
+            dm = fmad(mum[p + 1], gp[p + 1] - bm[p + 1], dm);
+        }
+        if (dmask) dmask[c.own] += (double)dm;
+    }
+#pragma unroll
+    for (int e = 0; e < 9; ++e) red[e][tid] = (double)G[e];
+    red[9][tid] = (double)dtau;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (tid < h)
+            for (int e = 0; e < kGradPartials; ++e) red[e][tid] += red[e][tid + h];
+        __syncthreads();
+    }
+    if (tid < kGradPartials) {
+        const uint32_t b = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        gpart[kGradPartials * (size_t)b + tid] += red[tid][0];
+    }
+}
+
+// Sum of per-work-group partials (m values per block) in a fixed order.
+__global__ __launch_bounds__(256) void k_sum_partials(const double *__restrict__ part, uint32_t nblocks, int m,
+                                                      double *__restrict__ out)
+{
+    __shared__ double red[256];
+    for (int e = 0; e < m; ++e) {
+        double acc = 0.0;
+        for (uint32_t b = threadIdx.x; b < nblocks; b += 256) acc += part[(size_t)m * b + e];
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        for (int h = 128; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[e] = red[0];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_fill(double *__restrict__ p, uint64_t n)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
 // ---- dispatch helpers ------------------------------------------------------------------------
 
 template <typename F> hipError_t by_lattice(int lattice, F &&f)
@@ -612,8 +960,8 @@ hipError_t launch_init(int lattice, int storage, int order, const Grid &g, const
 }
 
 hipError_t launch_step(int lattice, int storage, int order, const Grid &g, const StepConsts<double> &k64,
-                       const StepConsts<float> &k32, const uint32_t *links, const void *src, void *dst, int block_x,
-                       int block_y, int flags, hipStream_t stream)
+                       const StepConsts<float> &k32, const uint32_t *links, const float *gray, const void *src,
+                       void *dst, int block_x, int block_y, int flags, hipStream_t stream)
 {
     return by_lattice(lattice, [&](auto lat) {
         return by_storage(storage, [&](auto sv) {
@@ -629,20 +977,20 @@ hipError_t launch_step(int lattice, int storage, int order, const Grid &g, const
             m.nblocks = g3.x * g3.y * g3.z;
             m.xcd_slabs = (flags & kLaunchXcdSlabs) ? 1u : 0u;
             const dim3 grid(m.nblocks);
-            const bool general = links != nullptr || kc->forced;
+            const int mode = gray ? kGray : ((links != nullptr || kc->forced) ? kLinks : kPlain);
             const S *in = (const S *)src;
             S *out = (S *)dst;
+#define LBM_STEP(O, M) hipLaunchKernelGGL((k_step<LAT, S, O, M>), grid, block, 0, stream, in, out, g, *kc, m, links, gray)
             if (order == 2) {
-                if (general)
-                    hipLaunchKernelGGL((k_step<LAT, S, 2, true>), grid, block, 0, stream, in, out, g, *kc, m, links);
-                else
-                    hipLaunchKernelGGL((k_step<LAT, S, 2, false>), grid, block, 0, stream, in, out, g, *kc, m, links);
+                if (mode == kGray) LBM_STEP(2, kGray);
+                else if (mode == kLinks) LBM_STEP(2, kLinks);
+                else LBM_STEP(2, kPlain);
             } else {
-                if (general)
-                    hipLaunchKernelGGL((k_step<LAT, S, 3, true>), grid, block, 0, stream, in, out, g, *kc, m, links);
-                else
-                    hipLaunchKernelGGL((k_step<LAT, S, 3, false>), grid, block, 0, stream, in, out, g, *kc, m, links);
+                if (mode == kGray) LBM_STEP(3, kGray);
+                else if (mode == kLinks) LBM_STEP(3, kLinks);
+                else LBM_STEP(3, kPlain);
             }
+#undef LBM_STEP
             return hipGetLastError();
         });
     });
@@ -691,6 +1039,61 @@ hipError_t launch_permute(int lattice, int storage, int mode, const Grid &g, con
             return hipGetLastError();
         });
     });
+}
+
+hipError_t launch_seed(int lattice, int storage, const Grid &g, const StepConsts<double> &k64,
+                       const StepConsts<float> &k32, const void *src, void *lam, double *jpart, int kind, int plane,
+                       hipStream_t stream)
+{
+    return by_lattice(lattice, [&](auto lat) {
+        return by_storage(storage, [&](auto sv) {
+            using S = decltype(sv);
+            using C = typename Conv<S>::C;
+            constexpr int LAT = decltype(lat)::value;
+            const StepConsts<C> *kc;
+            if constexpr (sizeof(C) == 8) kc = &k64; else kc = &k32;
+            const dim3 grid = cell_grid(g, kBlockX, kRedThreads / kBlockX), block(kBlockX, kRedThreads / kBlockX);
+            hipLaunchKernelGGL((k_seed<LAT, S>), grid, block, 0, stream, (const S *)src, (C *)lam, jpart, g, *kc, kind,
+                               plane);
+            return hipGetLastError();
+        });
+    });
+}
+
+hipError_t launch_adjoint(int lattice, int storage, int order, const Grid &g, const StepConsts<double> &k64,
+                          const StepConsts<float> &k32, const void *state, const void *lam_in, void *lam_out,
+                          const float *gray, double *dmask, double *gpart, hipStream_t stream)
+{
+    return by_lattice(lattice, [&](auto lat) {
+        return by_storage(storage, [&](auto sv) {
+            using S = decltype(sv);
+            using C = typename Conv<S>::C;
+            constexpr int LAT = decltype(lat)::value;
+            const StepConsts<C> *kc;
+            if constexpr (sizeof(C) == 8) kc = &k64; else kc = &k32;
+            const dim3 grid = cell_grid(g, kBlockX, kRedThreads / kBlockX), block(kBlockX, kRedThreads / kBlockX);
+            if (order == 2)
+                hipLaunchKernelGGL((k_adjoint<LAT, S, 2>), grid, block, 0, stream, (const S *)state, (const C *)lam_in,
+                                   (C *)lam_out, gray, dmask, gpart, g, *kc);
+            else
+                hipLaunchKernelGGL((k_adjoint<LAT, S, 3>), grid, block, 0, stream, (const S *)state, (const C *)lam_in,
+                                   (C *)lam_out, gray, dmask, gpart, g, *kc);
+            return hipGetLastError();
+        });
+    });
+}
+
+hipError_t launch_sum(const double *part, uint32_t nblocks, int m, double *out, hipStream_t stream)
+{
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, stream, part, nblocks, m, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(double *p, uint64_t n, hipStream_t stream)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, stream, p, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_copy(void *dst, const void *src, int64_t nbytes, hipStream_t stream)

@@ -96,7 +96,8 @@ def test_prepare_weight_shift_and_diagnostic():
     (lambda p: setattr(p, "order", 4), lbm.LBM_ERR_ARG),
     (lambda p: setattr(p, "tensor_kind", 5), lbm.LBM_ERR_ARG),
     (lambda p: setattr(p, "shift_kind", 2), lbm.LBM_ERR_ARG),
-    (lambda p: setattr(p, "flags", 2), lbm.LBM_ERR_ARG),
+    (lambda p: setattr(p, "flags", 4), lbm.LBM_ERR_ARG),
+    (lambda p: setattr(p, "flags", 3), lbm.LBM_ERR_ARG),                  # mask and gray together
     (lambda p: p.force.__setitem__(1, float("nan")), lbm.LBM_ERR_ARG),
     (lambda p: setattr(p, "nx", 0), lbm.LBM_ERR_ARG),
     (lambda p: setattr(p, "nz", -3), lbm.LBM_ERR_ARG),
@@ -184,6 +185,7 @@ def test_null_context_calls_fail_cleanly():
         assert fn(*args) == lbm.LBM_ERR_ARG
     assert lbm._lib.lbm_time(None) == -1
     lbm.lbm_destroy(None)
-    spec = lbm.lbm_grad_spec()
-    assert lbm._lib.lbm_grad(None, ctypes.byref(spec), None, None, None) == lbm.LBM_ERR_UNSUPPORTED
+    spec = lbm.make_grad_spec("flux", 10, 5, 0)
+    assert lbm._lib.lbm_grad(None, ctypes.byref(spec), None, None, None, None, None) == lbm.LBM_ERR_ARG
+    assert lbm._lib.lbm_grad_workspace_bytes(None, ctypes.byref(spec)) == lbm.LBM_ERR_ARG
     assert lbm._lib.lbm_stream_copy(None, None, 16, None) == lbm.LBM_ERR_ARG

@@ -1,0 +1,199 @@
+"""Gradients by the hand-written adjoint (lbm_grad) against central finite differences of the
+FP64 oracle (the brute-force reference) and of the library's own FP64 forward."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+lbm = pytest.importorskip("paper_2605_27004_amd")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _case(lattice, shape, kind="theta", force=(1e-4, -5e-5, 2e-5), seed=3):
+    d = W.DIMS[lattice]
+    rng = np.random.default_rng(seed)
+    rho, s = W.random_fields(shape, d, seed, amp_rho=0.02, amp_s=0.03)
+    n = int(np.prod(shape))
+    gray = rng.uniform(0.0, 0.3, n)
+    gray[rng.uniform(size=n) < 0.1] = 1.0
+    t = W.config1_theta() if d == 2 else W.random_theta(seed)
+    if kind == "A":
+        t = W.pad3(np.linalg.inv(3.0 * t[:d, :d]))      # A with A^-1 = theta / cs^2
+    return dict(lattice=lattice, shape=shape, d=d, rho=rho, s=s, gray=gray, tensor=t, kind=kind, tau=0.8,
+                force=None if force is None else np.array(force[:d]))
+
+
+def _oracle_J(c, tensor, tau, gray, steps, objective, plane, ainv0):
+    """J after `steps` with the given parameters, the initial state built from the base tensor."""
+    name, shape, d = c["lattice"], c["shape"], c["d"]
+    f = oracle.init(name, shape, ainv0, c["rho"], c["s"])
+    ainv = oracle.tensor_to_ainv(np.asarray(tensor)[:d, :d], c["kind"], d)
+    oracle.steps_gray(name, shape, ainv, tau, f, steps, gray, force=c["force"])
+    return oracle.objective(name, shape, f, 0 if objective == "flux" else 1, plane, force=c["force"])
+
+
+def _gpu(c, storage, steps, objective, plane, ckpt, tensor=None, tau=None, gray=None, grad=True):
+    p = lbm.make_params(c["lattice"], storage, c["shape"], c["tensor"] if tensor is None else tensor, c["kind"],
+                        c["tau"] if tau is None else tau, force=c["force"], gray=True)
+    sim = lbm.Simulation(p, c["rho"], c["s"], mask=(c["gray"] if gray is None else gray).astype(np.float32))
+    if grad:
+        j, dt, du, dm = sim.grad(objective, steps, ckpt, plane)
+        return j, np.array(dt), du, dm.cpu().numpy()
+    sim.step(steps)
+    return sim
+
+
+CASES = [("D2Q9", (16, 12, 1), "theta", "kinetic_energy"), ("D2Q9", (16, 12, 1), "theta", "flux"),
+         ("D3Q19", (8, 6, 5), "A", "kinetic_energy"), ("D3Q27", (7, 6, 5), "theta", "flux")]
+
+
+@pytest.mark.parametrize("lattice,shape,kind,objective", CASES)
+def test_adjoint_matches_oracle_finite_differences(lattice, shape, kind, objective):
+    c = _case(lattice, shape, kind)
+    steps, ckpt, plane = 23, 5, 3
+    d = c["d"]
+    # the gray field is stored in single precision by the library; the oracle uses the same values
+    gray = c["gray"].astype(np.float32).astype(np.float64)
+    c["gray"] = gray
+    ainv0 = oracle.tensor_to_ainv(c["tensor"][:d, :d], kind, d)
+    j, dt, du, dm = _gpu(c, "f64", steps, objective, plane, ckpt)
+    j0 = _oracle_J(c, c["tensor"], c["tau"], gray, steps, objective, plane, ainv0)
+    assert abs(j - j0) <= 1e-12 * abs(j0)
+    # central differences: truncation ~ h^2, rounding ~ eps |J| / h; the gate is 1e-6 of the
+    # derivative plus 1e-9 of |J| (above both for these step sizes)
+    def close(g, fd):
+        return abs(g - fd) <= 1e-6 * abs(fd) + 1e-9 * abs(j0)
+
+    for a in range(d):
+        for b in range(a, d):
+            h = 1e-5
+            tp = c["tensor"].copy(); tm = c["tensor"].copy()
+            tp[a, b] += h; tm[a, b] -= h
+            if a != b:
+                tp[b, a] += h; tm[b, a] -= h
+            fd = (_oracle_J(c, tp, c["tau"], gray, steps, objective, plane, ainv0)
+                  - _oracle_J(c, tm, c["tau"], gray, steps, objective, plane, ainv0)) / (2 * h)
+            assert close(dt[a, b], fd), (a, b, dt[a, b], fd)
+    h = 1e-5
+    fd = (_oracle_J(c, c["tensor"], c["tau"] + h, gray, steps, objective, plane, ainv0)
+          - _oracle_J(c, c["tensor"], c["tau"] - h, gray, steps, objective, plane, ainv0)) / (2 * h)
+    assert close(du, fd), (du, fd)
+    rng = np.random.default_rng(7)
+    h = 1e-4
+    for cell in rng.choice(len(gray), 4, replace=False):
+        gp = gray.copy(); gm = gray.copy()
+        gp[cell] += h; gm[cell] -= h
+        fd = (_oracle_J(c, c["tensor"], c["tau"], gp, steps, objective, plane, ainv0)
+              - _oracle_J(c, c["tensor"], c["tau"], gm, steps, objective, plane, ainv0)) / (2 * h)
+        assert close(dm[cell], fd), (cell, dm[cell], fd)
+
+
+def test_adjoint_matches_gpu_finite_differences_no_force():
+    """Without a force, against central differences of the library's own FP64 forward. The
+    initial populations are those of the base parameters; the K-independent weight shift makes
+    the stored deviations mean the same populations in every context."""
+    c = _case("D3Q19", (9, 7, 6), force=None, seed=5)
+    steps, ckpt = 30, 30
+    gray = c["gray"].astype(np.float32)
+
+    def sim_for(tensor, tau):
+        p = lbm.make_params(c["lattice"], "f64", c["shape"], tensor, "theta", tau, shift="weight", gray=True)
+        return lbm.Simulation(p, c["rho"], c["s"], mask=gray)
+
+    base = sim_for(c["tensor"], c["tau"])
+    snap = base.get_populations()
+    j, dt, du, _ = base.grad("kinetic_energy", steps, ckpt, 0, want_dmask=False)
+
+    def J(tensor, tau):
+        sim = sim_for(tensor, tau)
+        sim.set_populations(snap)
+        return sim.grad("kinetic_energy", steps, ckpt, 0, want_dmask=False)[0]
+
+    h = 1e-4
+    fd = (J(c["tensor"], c["tau"] + h) - J(c["tensor"], c["tau"] - h)) / (2 * h)
+    assert abs(du - fd) <= 1e-6 * abs(fd) + 1e-9 * abs(j)
+    h = 1e-5
+    tp = c["tensor"].copy(); tm = c["tensor"].copy()
+    tp[0, 1] += h; tp[1, 0] += h; tm[0, 1] -= h; tm[1, 0] -= h
+    fd = (J(tp, c["tau"]) - J(tm, c["tau"])) / (2 * h)
+    assert abs(dt[0][1] - fd) <= 1e-6 * abs(fd) + 1e-9 * abs(j)
+
+
+@pytest.mark.parametrize("ckpt", [1, 4, 23, 50])
+def test_checkpoint_interval_does_not_change_gradients(ckpt):
+    c = _case("D2Q9", (12, 10, 1))
+    ref = _gpu(c, "f64", 23, "flux", 2, 100)
+    got = _gpu(c, "f64", 23, "flux", 2, ckpt)
+    assert got[0] == ref[0]
+    assert np.array_equal(got[1], ref[1]) and got[2] == ref[2] and np.array_equal(got[3], ref[3])
+
+
+def test_fp32_adjoint_close_to_fp64():
+    c = _case("D3Q19", (10, 8, 6))
+    a = _gpu(c, "f64", 40, "kinetic_energy", 0, 10)
+    b = _gpu(c, "f32", 40, "kinetic_energy", 0, 10)
+    assert abs(b[0] - a[0]) <= 1e-5 * abs(a[0])
+    assert np.abs(b[1] - a[1]).max() <= 1e-3 * np.abs(a[1]).max()
+    assert abs(b[2] - a[2]) <= 1e-3 * abs(a[2])
+    assert np.abs(b[3] - a[3]).max() <= 1e-3 * np.abs(a[3]).max()
+
+
+def test_grad_advances_like_step():
+    c = _case("D2Q9", (12, 10, 1))
+    p = lbm.make_params(c["lattice"], "f64", c["shape"], c["tensor"], "theta", c["tau"], force=c["force"], gray=True)
+    a = lbm.Simulation(p, c["rho"], c["s"], mask=c["gray"].astype(np.float32))
+    b = lbm.Simulation(p, c["rho"], c["s"], mask=c["gray"].astype(np.float32))
+    a.grad("flux", 17, 4, 1)
+    b.step(17)
+    assert a.t == b.t == 17
+    assert torch.equal(a.f64(), b.f64())
+
+
+def test_gray_forward_matches_oracle():
+    c = _case("D3Q27", (9, 8, 7))
+    gray = c["gray"].astype(np.float32)
+    p = lbm.make_params(c["lattice"], "f64", c["shape"], c["tensor"], "theta", c["tau"], force=c["force"], gray=True)
+    sim = lbm.Simulation(p, c["rho"], c["s"], mask=gray)
+    sim.step(40)
+    f = sim.f64().cpu().numpy()
+    ainv = oracle.tensor_to_ainv(c["tensor"], "theta", 3)
+    fo = oracle.init(c["lattice"], c["shape"], ainv, c["rho"], c["s"])
+    oracle.steps_gray(c["lattice"], c["shape"], ainv, c["tau"], fo, 40, gray.astype(np.float64), force=c["force"])
+    _, _, cc, _, _ = lbm.lbm_lattice_info(lbm.LBM_D3Q27)
+    oc, _, _ = oracle.lattice("D3Q27")
+    perm = [next(k for k in range(27) if list(oc[k]) == cc[i]) for i in range(27)]
+    assert np.abs(f - fo[perm]).max() <= 1e-12 * np.abs(fo).max()
+
+
+def test_grad_rejects_unsupported():
+    c = _case("D2Q9", (8, 8, 1))
+    p = lbm.make_params("D2Q9", "f64", (8, 8, 1), c["tensor"], "theta", 0.8, masked=True)
+    sim = lbm.Simulation(p, c["rho"], c["s"], mask=np.zeros(64, np.uint8))
+    with pytest.raises(lbm.LBMError) as ei:
+        sim.grad("flux", 3, 1, 0)
+    assert ei.value.code == lbm.LBM_ERR_UNSUPPORTED
+
+
+def test_autograd_function():
+    c = _case("D2Q9", (10, 8, 1))
+    fn = lbm.Objective.function()
+    cfg = dict(lattice="D2Q9", storage="f64", shape=c["shape"], rho=c["rho"], s=c["s"], force=c["force"],
+               objective="kinetic_energy", nsteps=12, checkpoint_every=5)
+    tensor = torch.tensor(c["tensor"], dtype=torch.float64, requires_grad=True)
+    tau = torch.tensor(0.8, dtype=torch.float64, requires_grad=True)
+    gray = torch.tensor(c["gray"], dtype=torch.float32, device="cuda", requires_grad=True)
+    j = fn.apply(tensor, tau, gray, cfg)
+    (2.0 * j).backward()
+    j2, dt, du, dm = _gpu(c, "f64", 12, "kinetic_energy", 0, 5)
+    assert float(j) == j2
+    assert np.allclose(tensor.grad.numpy(), 2 * dt) and abs(float(tau.grad) - 2 * du) < 1e-15
+    assert np.allclose(gray.grad.cpu().numpy(), 2 * dm, rtol=1e-6)
