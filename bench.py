@@ -13,8 +13,11 @@ stream-and-collide pass over the whole grid. Prints ONE JSON line:
   cpu_baseline the FP64 oracle on the host cores, a bounded sample of the same workload
   variants     FP16 / BF16 shifted-deviation storage and FP64 storage of the same workload:
                MLUPS, roofline fraction and the per-field error against the FP64 path
+  adjoint      gradient workload (D2Q9 512^2 and D3Q19 128^3 channels with gray obstacles,
+               2000 steps, checkpoints every 100, FP32): time of lbm_grad (forward + reverse
+               sweep) over the time of the forward pass alone; adjoint_fwd_ratio = D3Q19's
 
-Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-variants]
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-variants] [--no-adjoint]
 """
 import argparse
 import hashlib
@@ -40,6 +43,7 @@ def parse():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
     return ap.parse_args()
 
@@ -191,7 +195,33 @@ def main():
         del got, ref
         torch.cuda.empty_cache()
         line["variants"] = variants
-    line["adjoint_fwd_ratio"] = None
+    # ---- gradient workload: adjoint/forward time ratio ----
+    if not args.no_adjoint:
+        adj = {}
+        for lat in ("D2Q9", "D3Q19"):
+            wl4 = W.config4(lat)
+            gray = torch.as_tensor(wl4.meta["gray"].astype(np.float32), device="cuda")
+            p4 = lbm.make_params(lat, "f32", wl4.shape, wl4.tensor, "theta", wl4.tau, force=wl4.meta["force"],
+                                 gray=True)
+            sim4 = lbm.Simulation(p4, wl4.rho, wl4.s, mask=gray)
+            sim4.grad("flux", 20, 10, wl4.meta["outlet_plane"], want_dmask=True)   # warm-up
+            t_fwd = timed_steps(sim4, wl4.steps, 0, torch)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            jv, _, _, _ = sim4.grad("flux", wl4.steps, wl4.meta["checkpoint_every"], wl4.meta["outlet_plane"])
+            torch.cuda.synchronize()
+            t_grad = time.perf_counter() - t0
+            adj[lat] = {"grid": list(wl4.shape), "steps": wl4.steps, "checkpoint_every": wl4.meta["checkpoint_every"],
+                        "forward_s": round(t_fwd, 4), "forward_plus_adjoint_s": round(t_grad, 4),
+                        "ratio_total": round(t_grad / t_fwd, 3), "ratio_backward": round((t_grad - t_fwd) / t_fwd, 3),
+                        "objective": jv}
+            sim4.close()
+            del sim4, gray
+            torch.cuda.empty_cache()
+        line["adjoint"] = adj
+        line["adjoint_fwd_ratio"] = adj["D3Q19"]["ratio_total"]
+    else:
+        line["adjoint_fwd_ratio"] = None
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample of the same workload ----
     if not args.no_cpu_baseline:

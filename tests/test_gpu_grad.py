@@ -197,3 +197,60 @@ def test_autograd_function():
     assert float(j) == j2
     assert np.allclose(tensor.grad.numpy(), 2 * dt) and abs(float(tau.grad) - 2 * du) < 1e-15
     assert np.allclose(gray.grad.cpu().numpy(), 2 * dm, rtol=1e-6)
+
+
+@pytest.mark.parametrize("lattice", ["D2Q9", "D3Q19"])
+def test_gradient_workload_full_size(lattice):
+    """The gradient workload at full size (D2Q9 512^2 / D3Q19 128^3 channel with obstacles,
+    2000 steps, checkpoints every 100, outlet flux): the FP64 adjoint against central
+    differences of the FP64 forward with the initial state held fixed, and the FP32 adjoint
+    (the configured precision) against the FP64 one."""
+    wl = W.config4(lattice)
+    gray = wl.meta["gray"].astype(np.float32)
+    plane, ck, steps = wl.meta["outlet_plane"], wl.meta["checkpoint_every"], wl.steps
+
+    def sim_for(storage, tensor=None, tau=None, g=None):
+        p = lbm.make_params(lattice, storage, wl.shape, wl.tensor if tensor is None else tensor, "theta",
+                            wl.tau if tau is None else tau, force=wl.meta["force"], gray=True, shift="weight")
+        return lbm.Simulation(p, wl.rho, wl.s, mask=gray if g is None else g)
+
+    base = sim_for("f64")
+    snap = base.get_populations()
+    j, dt, du, dm = base.grad("flux", steps, ck, plane)
+    dm = dm.cpu().numpy()
+    print(f"[grad] {lattice} J={j:.6e} dtau={du:.6e} dT={np.array(dt).ravel()[:3]}", flush=True)
+
+    def J(**kw):
+        sim = sim_for("f64", **kw)
+        sim.set_populations(snap)
+        sim.step(steps)
+        rho, s, _ = sim.moments()
+        n = wl.shape
+        flux = (rho * s[0]).reshape(n[2], n[1], n[0])[:, :, plane]
+        return float(flux.sum())
+
+    def close(g, fd):
+        return abs(g - fd) <= 1e-5 * abs(fd) + 1e-9 * abs(j)
+
+    h = 1e-4
+    fd = (J(tau=wl.tau + h) - J(tau=wl.tau - h)) / (2 * h)
+    assert close(du, fd), (du, fd)
+    h = 1e-5
+    tp = wl.tensor.copy(); tm = wl.tensor.copy()
+    tp[0, 1] += h; tp[1, 0] += h; tm[0, 1] -= h; tm[1, 0] -= h
+    fd = (J(tensor=tp) - J(tensor=tm)) / (2 * h)
+    assert close(dt[0][1], fd), (dt[0][1], fd)
+    h = 1e-3
+    for cell in np.argsort(-np.abs(dm))[:2]:
+        gp = gray.copy(); gm = gray.copy()
+        gp[cell] += h; gm[cell] -= h
+        fd = (J(g=gp) - J(g=gm)) / (2 * h)
+        # the FP32 gray field limits the perturbation's exactness to 2^-24 relative of h
+        assert abs(dm[cell] - fd) <= 1e-4 * abs(fd) + 1e-9 * abs(j), (cell, dm[cell], fd)
+    f32 = sim_for("f32")
+    j32, dt32, du32, dm32 = f32.grad("flux", steps, ck, plane)
+    dm32 = dm32.cpu().numpy()
+    print(f"[grad] {lattice} f32 vs f64: J {abs(j32 / j - 1):.2e} dtau {abs(du32 / du - 1):.2e} "
+          f"dm {np.abs(dm32 - dm).max() / np.abs(dm).max():.2e}", flush=True)
+    assert abs(j32 / j - 1) < 1e-4 and abs(du32 / du - 1) < 1e-2
+    assert np.abs(dm32 - dm).max() <= 1e-2 * np.abs(dm).max()

@@ -239,6 +239,44 @@ def config3(n: int = 512, steps: int = 1000, seed: int = 0) -> Workload:
     return wl
 
 
+def obstacle_channel(shape, seed: int = 0, count: int = 24, radius=(0.03, 0.09)) -> np.ndarray:
+    """Gray field (float64 [N], 1 = solid, 0 = fluid) of a channel: solid walls on the y faces
+    (and z faces in 3-D) plus `count` seeded random cylinders (2-D) or spheres (3-D). Each
+    obstacle draws its centre (uniform in the interior) and then its radius (uniform in
+    `radius` times the smallest extent); the domain is periodic along x."""
+    nx, ny, nz = shape
+    d = 2 if nz == 1 else 3
+    x, y, z = grid(shape)
+    gray = ((y == 0) | (y == ny - 1)).astype(np.float64)
+    if d == 3:
+        gray = np.maximum(gray, ((z == 0) | (z == nz - 1)).astype(np.float64))
+    rng = np.random.default_rng(seed)
+    ext = min(nx, ny, nz) if d == 3 else min(nx, ny)
+    for _ in range(count):
+        c = rng.uniform(0.0, 1.0, 3) * np.array([nx, ny - 2, max(nz - 2, 1)]) + np.array([0.0, 1.0, 1.0])
+        r = rng.uniform(radius[0], radius[1]) * ext
+        dx = (x - c[0] + nx / 2) % nx - nx / 2          # periodic along x
+        dist2 = dx * dx + (y - c[1]) ** 2 + ((z - c[2]) ** 2 if d == 3 else 0.0)
+        gray[dist2 <= r * r] = 1.0
+    return gray
+
+
+def config4(lattice: str = "D2Q9", steps: int = 2000, seed: int = 0) -> Workload:
+    """Gradient workload: D2Q9 512 x 512 or D3Q19 128^3 channel with random cylinders / spheres
+    (gray cells), body force 1e-5 along x, tau = 0.8, started at rest; objective = mass flux
+    through the outlet plane x = nx - 1, checkpoints every 100 steps."""
+    shape = (512, 512, 1) if lattice == "D2Q9" else (128, 128, 128)
+    d = DIMS[lattice]
+    rho, s = uniform_fields(shape, d)
+    t = config1_theta() if d == 2 else random_theta(seed)
+    wl = Workload(lattice, shape, t, "theta", 0.8, steps, rho, s, None, name=f"{lattice.lower()}_channel")
+    wl.meta["gray"] = obstacle_channel(shape, seed)
+    wl.meta["force"] = np.array([1e-5, 0.0, 0.0])[:d]
+    wl.meta["outlet_plane"] = shape[0] - 1
+    wl.meta["checkpoint_every"] = 100
+    return wl
+
+
 def channel_mask(shape, wall_axis: int = 1) -> np.ndarray:
     """Solid planes at index 0 and n-1 along `wall_axis` (a plane channel), uint8 [N]."""
     x = grid(shape)[wall_axis]
