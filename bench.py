@@ -159,7 +159,7 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_GBPS, 4), "traffic": traffic_per_launch(),
-                     "algorithmic_bytes_per_launch": alg_bytes, "kernel": "k_step<D3Q19, float, 3>",
+                     "algorithmic_bytes_per_launch": alg_bytes, "kernel": "k_step<D3Q19, float, order 3, plain>",
                      "copy_kernel_GBps": round(copy_gbps, 1), "frac_of_copy": round(achieved / copy_gbps, 4)},
         "mass_total": tot[0],
     }
