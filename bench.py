@@ -16,8 +16,11 @@ stream-and-collide pass over the whole grid. Prints ONE JSON line:
   adjoint      gradient workload (D2Q9 512^2 and D3Q19 128^3 channels with gray obstacles,
                2000 steps, checkpoints every 100, FP32): time of lbm_grad (forward + reverse
                sweep) over the time of the forward pass alone; adjoint_fwd_ratio = D3Q19's
+  batched      512 independent D3Q19 domains (edges 16..64, own tensor and tau each), FP32,
+               500 steps: the autotuned schedule's MLUPS and fraction of the 8 TB/s peak, beside
+               fixed step-per-launch and persistent schedules
 
-Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-variants] [--no-adjoint]
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-variants] [--no-adjoint] [--no-batched]
 """
 import argparse
 import hashlib
@@ -44,6 +47,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=3)
     return ap.parse_args()
 
@@ -222,6 +226,43 @@ def main():
         line["adjoint_fwd_ratio"] = adj["D3Q19"]["ratio_total"]
     else:
         line["adjoint_fwd_ratio"] = None
+
+    # ---- batched small domains: one schedule picked by the autotuner ----
+    if not args.no_batched:
+        wl5 = W.config5()
+        bt = lbm.Batch(wl5.lattice, "f32", wl5.domains)
+        chosen, tune_ms = bt.autotune(trial_steps=20)
+
+        def time_batch(steps):
+            bt.step(5)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(bt.stream)
+            bt.step(steps)
+            e1.record(bt.stream)
+            torch.cuda.synchronize()
+            bt.status()
+            return e0.elapsed_time(e1) / 1e3
+
+        def figures(sec):
+            return {"MLUPS": round(wl5.cells * wl5.steps / sec / 1e6, 1),
+                    "frac": round(152.0 * wl5.cells * wl5.steps / sec / 1e9 / PEAK_GBPS, 4),
+                    "ms_per_step": round(sec / wl5.steps * 1e3, 4)}
+
+        res = {"domains": len(wl5.domains), "cells": wl5.cells, "steps": wl5.steps, "storage": "f32",
+               "autotuned": dict(schedule=chosen, trial_ms_per_step=round(tune_ms, 4), **figures(time_batch(wl5.steps)))}
+        fixed = {"stepwise_xcd": dict(mode="stepwise", xcd_group=1),
+                 "persistent_all": dict(mode="persistent", xcd_group=1, wg_per_cu=2, chunk_cells=65536, group_bytes=0),
+                 "persistent_groups": dict(mode="persistent", xcd_group=1, wg_per_cu=2, chunk_cells=4096,
+                                           group_bytes=192 << 20)}
+        for name, sch in fixed.items():
+            bt.set_schedule(**sch)
+            res[name] = figures(time_batch(wl5.steps))
+        bt.close()
+        del bt
+        torch.cuda.empty_cache()
+        line["batched"] = res
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample of the same workload ----
     if not args.no_cpu_baseline:

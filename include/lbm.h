@@ -237,6 +237,109 @@ const char *lbm_last_error(void);
  * streaming copy kernel on stream; the reference for achievable HBM bandwidth. */
 int lbm_stream_copy(void *dst, const void *src, int64_t nbytes, void *stream);
 
+/* ---- batches of independent domains ----------------------------------------------------
+ *
+ * A batch advances many independent periodic domains of uneven sizes together, each with its
+ * own tensor and tau, by eq:LBE_BGK with the equilibrium above: every domain follows exactly
+ * the update a single-grid context with the same parameters performs (bitwise the same), so
+ * the batch is a throughput device for many small problems, not a different method.
+ * Shared by all domains: lattice, storage, order, shift kind and rho0. No masks, gray cells
+ * or body force in a batch.
+ *
+ * Layout. Domain d has N_d = nx*ny*nz cells. Per-cell host-visible arrays (rho, s, FP64
+ * exports) concatenate the domains in order: domain d starts at cell offset
+ * C_d = N_0 + ... + N_{d-1} (lbm_batch_cells); rho is [C], s is [d][C] with C the total. The
+ * population arrays are opaque (lbm_batch_pop_bytes each). */
+typedef struct lbm_batch lbm_batch;
+
+typedef struct lbm_domain {
+    int64_t nx, ny, nz;  /* extents, >= 1 (nz = 1 for D2Q9), N_d < 2^31                  */
+    int32_t tensor_kind; /* LBM_TENSOR_*                                                  */
+    int32_t reserved;    /* must be 0                                                     */
+    double tensor[9];    /* as in lbm_params                                              */
+    double tau;          /* > 1/2                                                         */
+} lbm_domain;
+
+typedef struct lbm_batch_params {
+    int32_t lattice, storage, order, shift_kind; /* as in lbm_params                      */
+    double rho0;                                 /* as in lbm_params                      */
+    int64_t ndomains;                            /* >= 1                                  */
+    const lbm_domain *domains;                   /* host array [ndomains], read during the call */
+} lbm_batch_params;
+
+/* Total cells C; with offsets non-NULL also writes offsets[d] = C_d for d <= ndomains (host,
+ * [ndomains + 1]). Negative LBM_ERR_* if the parameters are invalid. */
+int64_t lbm_batch_cells(const lbm_batch_params *p, int64_t *offsets);
+/* Bytes of ONE population array (the batch needs two) and of the device scratch. */
+int64_t lbm_batch_pop_bytes(const lbm_batch_params *p);
+int64_t lbm_batch_scratch_bytes(const lbm_batch_params *p);
+
+/* Create a batch: validate every domain (as lbm_init does), upload the per-domain constants
+ * and tile tables into scratch, and write f(0) = f^eq(rho0, s0) of every domain.
+ *   pop_a, pop_b: device, lbm_batch_pop_bytes each, 256-byte aligned.
+ *   scratch:      device, lbm_batch_scratch_bytes, 256-byte aligned.
+ *   rho0, s0:     device FP64 [C] and [d][C], read during the call.
+ * Synchronises the stream before returning. Starts with the step-per-launch schedule. */
+int lbm_batch_init(lbm_batch **out, const lbm_batch_params *p, void *pop_a, void *pop_b, void *scratch,
+                   const double *rho0, const double *s0, void *hip_stream);
+
+/* How the steps are run. Results never depend on it (bitwise). */
+#define LBM_BATCH_STEPWISE 0   /* one launch per step, one work-group per 256-cell tile       */
+#define LBM_BATCH_PERSISTENT 1 /* one cooperative launch for all steps of an lbm_batch_step  */
+typedef struct lbm_batch_schedule {
+    int32_t mode;        /* LBM_BATCH_STEPWISE or LBM_BATCH_PERSISTENT                        */
+    int32_t xcd_group;   /* 1: place each domain's work on one XCD (flat work-group b runs
+                            on XCD b mod 8); 0: domain-major order                             */
+    int32_t wg_per_cu;   /* persistent: resident work-groups per compute unit, 1 .. the
+                            kernel's occupancy (lbm_batch_set_schedule checks)                 */
+    int32_t reserved;    /* must be 0                                                          */
+    int64_t chunk_cells; /* persistent: most cells one work-group takes from one domain per
+                            step, a multiple of 256                                            */
+    int64_t group_bytes; /* persistent: 0 = every domain in one group; else domains are run
+                            in consecutive groups whose two population arrays total at most
+                            this many bytes (a lone larger domain forms its own group), each
+                            group through all steps before the next                            */
+} lbm_batch_schedule;
+
+/* Build and upload the work lists of a schedule (synchronises the stream). */
+int lbm_batch_set_schedule(lbm_batch *b, const lbm_batch_schedule *s);
+int lbm_batch_get_schedule(const lbm_batch *b, lbm_batch_schedule *s);
+
+/* Measure a fixed set of candidate schedules (step-per-launch with and without XCD
+ * placement; persistent over work-groups per CU, chunk sizes and group sizes) on the batch's
+ * own state, trial_steps timed steps each after two untimed ones, and keep the fastest. The
+ * state is saved to `backup` (device, lbm_batch_pop_bytes, 256-byte aligned) first and
+ * restored afterwards, so the batch's time and state are unchanged. best (host, may be NULL)
+ * receives the chosen schedule and best_ms (may be NULL) its time per step. Synchronises. */
+int lbm_batch_autotune(lbm_batch *b, void *backup, int32_t trial_steps, lbm_batch_schedule *best, double *best_ms);
+
+/* Advance every domain by nsteps (asynchronous). */
+int lbm_batch_step(lbm_batch *b, int64_t nsteps);
+
+/* Synchronise and report the outcome of earlier persistent launches: LBM_ERR_HIP if a
+ * work-group's bounded wait ran out (the state is then undefined), else LBM_OK. */
+int lbm_batch_status(lbm_batch *b);
+
+/* rho [C] and s [d][C] (device FP64, either may be NULL) of the canonical state, and
+ * totals (host FP64 [ndomains][4], may be NULL): per domain sum rho and sum rho s. Checks
+ * the status as lbm_batch_status does; synchronises when totals is non-NULL. */
+int lbm_batch_moments(lbm_batch *b, double *rho, double *s, double *totals);
+
+/* Canonical pre-collision populations in FP64 (sigma added back): device [q * C], domain d
+ * at offset q * C_d as [q][N_d] in the canonical velocity order. */
+int lbm_batch_get_f64(lbm_batch *b, double *out);
+
+/* Steps taken since lbm_batch_init (-1 if b is NULL). */
+int64_t lbm_batch_time(const lbm_batch *b);
+
+/* Set the spin limit of the persistent schedule's bounded waits (polls of a counter; the
+ * default covers seconds). A tiny value makes waits give up; tests use it to exercise the
+ * failure path. */
+int lbm_batch_set_spin_limit(lbm_batch *b, uint32_t polls);
+
+/* Free a batch (NULL is allowed). Does not touch the caller's buffers. */
+void lbm_batch_destroy(lbm_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

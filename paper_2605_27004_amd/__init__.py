@@ -63,6 +63,31 @@ class lbm_grad_spec(ctypes.Structure):
 OBJECTIVES = {"flux": 0, "kinetic_energy": 1}
 
 
+class lbm_domain(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64),
+                ("tensor_kind", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("tensor", ctypes.c_double * 9), ("tau", ctypes.c_double)]
+
+
+class lbm_batch_params(ctypes.Structure):
+    _fields_ = [("lattice", ctypes.c_int32), ("storage", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("shift_kind", ctypes.c_int32), ("rho0", ctypes.c_double), ("ndomains", ctypes.c_int64),
+                ("domains", ctypes.POINTER(lbm_domain))]
+
+
+class lbm_batch_schedule(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("xcd_group", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("chunk_cells", ctypes.c_int64), ("group_bytes", ctypes.c_int64)]
+
+    def as_dict(self) -> dict:
+        return {"mode": "persistent" if self.mode == LBM_BATCH_PERSISTENT else "stepwise",
+                "xcd_group": int(self.xcd_group), "wg_per_cu": int(self.wg_per_cu),
+                "chunk_cells": int(self.chunk_cells), "group_bytes": int(self.group_bytes)}
+
+
+LBM_BATCH_STEPWISE, LBM_BATCH_PERSISTENT = 0, 1
+
+
 class LBMError(RuntimeError):
     def __init__(self, code: int, message: str):
         super().__init__(f"[{code}] {message}")
@@ -99,6 +124,21 @@ def _bind(path: str):
         "lbm_destroy": (None, [vp]),
         "lbm_last_error": (ctypes.c_char_p, []),
         "lbm_stream_copy": (ctypes.c_int, [vp, vp, i64, vp]),
+        "lbm_batch_cells": (i64, [ctypes.POINTER(lbm_batch_params), ctypes.POINTER(ctypes.c_int64)]),
+        "lbm_batch_pop_bytes": (i64, [ctypes.POINTER(lbm_batch_params)]),
+        "lbm_batch_scratch_bytes": (i64, [ctypes.POINTER(lbm_batch_params)]),
+        "lbm_batch_init": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(lbm_batch_params), vp, vp, vp, vp, vp,
+                                          vp]),
+        "lbm_batch_set_schedule": (ctypes.c_int, [vp, ctypes.POINTER(lbm_batch_schedule)]),
+        "lbm_batch_get_schedule": (ctypes.c_int, [vp, ctypes.POINTER(lbm_batch_schedule)]),
+        "lbm_batch_autotune": (ctypes.c_int, [vp, vp, i32, ctypes.POINTER(lbm_batch_schedule), dp]),
+        "lbm_batch_step": (ctypes.c_int, [vp, i64]),
+        "lbm_batch_status": (ctypes.c_int, [vp]),
+        "lbm_batch_moments": (ctypes.c_int, [vp, vp, vp, dp]),
+        "lbm_batch_get_f64": (ctypes.c_int, [vp, vp]),
+        "lbm_batch_time": (i64, [vp]),
+        "lbm_batch_set_spin_limit": (ctypes.c_int, [vp, ctypes.c_uint32]),
+        "lbm_batch_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -267,6 +307,118 @@ def lbm_stream_copy(dst, src, nbytes: int, stream=None) -> None:
     _check(_lib.lbm_stream_copy(_ptr(dst), _ptr(src), int(nbytes), _ptr(stream)))
 
 
+# ---- batches of independent domains ---------------------------------------------------------
+
+def make_batch_params(lattice, storage, domains, order=3, shift="rest", rho0=1.0) -> lbm_batch_params:
+    """Batch parameters from a list of dicts with keys shape (nx, ny, nz), tensor (3 x 3),
+    tensor_kind and tau. The ctypes domain array is kept on the returned object."""
+    arr = (lbm_domain * len(domains))()
+    for i, dm in enumerate(domains):
+        nx, ny, nz = (tuple(dm["shape"]) + (1,))[:3]
+        arr[i].nx, arr[i].ny, arr[i].nz = int(nx), int(ny), int(nz)
+        arr[i].tensor_kind = TENSOR_KINDS[dm.get("tensor_kind", "theta")]
+        arr[i].reserved = 0
+        arr[i].tensor[:] = _flat9(dm["tensor"])
+        arr[i].tau = float(dm["tau"])
+    p = lbm_batch_params()
+    p.lattice = LATTICES[lattice] if isinstance(lattice, str) else int(lattice)
+    p.storage = STORAGES[storage] if isinstance(storage, str) else int(storage)
+    p.order = int(order)
+    p.shift_kind = SHIFTS[shift] if isinstance(shift, str) else int(shift)
+    p.rho0 = float(rho0)
+    p.ndomains = len(domains)
+    p.domains = ctypes.cast(arr, ctypes.POINTER(lbm_domain))
+    p._keep = arr
+    return p
+
+
+def make_batch_schedule(mode="stepwise", xcd_group=0, wg_per_cu=0, chunk_cells=0, group_bytes=0):
+    s = lbm_batch_schedule()
+    s.mode = LBM_BATCH_PERSISTENT if mode == "persistent" else LBM_BATCH_STEPWISE
+    s.xcd_group, s.wg_per_cu, s.reserved = int(xcd_group), int(wg_per_cu), 0
+    s.chunk_cells, s.group_bytes = int(chunk_cells), int(group_bytes)
+    return s
+
+
+def lbm_batch_cells(p: lbm_batch_params):
+    """(total cells C, per-domain cell offsets [ndomains + 1] as a list)."""
+    offs = (ctypes.c_int64 * (p.ndomains + 1))()
+    c = _lib.lbm_batch_cells(ctypes.byref(p), offs)
+    if c < 0:
+        _check(int(c))
+    return int(c), list(offs)
+
+
+def lbm_batch_pop_bytes(p: lbm_batch_params) -> int:
+    b = _lib.lbm_batch_pop_bytes(ctypes.byref(p))
+    if b < 0:
+        _check(int(b))
+    return int(b)
+
+
+def lbm_batch_scratch_bytes(p: lbm_batch_params) -> int:
+    b = _lib.lbm_batch_scratch_bytes(ctypes.byref(p))
+    if b < 0:
+        _check(int(b))
+    return int(b)
+
+
+def lbm_batch_init(p: lbm_batch_params, pop_a, pop_b, scratch, rho0, s0, stream=None) -> int:
+    out = ctypes.c_void_p()
+    _check(_lib.lbm_batch_init(ctypes.byref(out), ctypes.byref(p), _ptr(pop_a), _ptr(pop_b), _ptr(scratch),
+                               _ptr(rho0), _ptr(s0), _ptr(stream)))
+    return out.value
+
+
+def lbm_batch_set_schedule(b: int, s: lbm_batch_schedule) -> None:
+    _check(_lib.lbm_batch_set_schedule(b, ctypes.byref(s)))
+
+
+def lbm_batch_get_schedule(b: int) -> lbm_batch_schedule:
+    s = lbm_batch_schedule()
+    _check(_lib.lbm_batch_get_schedule(b, ctypes.byref(s)))
+    return s
+
+
+def lbm_batch_autotune(b: int, backup, trial_steps: int = 20):
+    """(chosen schedule, its ms per step)."""
+    s = lbm_batch_schedule()
+    ms = ctypes.c_double()
+    _check(_lib.lbm_batch_autotune(b, _ptr(backup), int(trial_steps), ctypes.byref(s), ctypes.byref(ms)))
+    return s, ms.value
+
+
+def lbm_batch_step(b: int, nsteps: int) -> None:
+    _check(_lib.lbm_batch_step(b, int(nsteps)))
+
+
+def lbm_batch_status(b: int) -> None:
+    _check(_lib.lbm_batch_status(b))
+
+
+def lbm_batch_moments(b: int, rho=None, s=None, ndomains: int = 0):
+    """Per-domain totals [ndomains][4] (sum rho, sum rho s) as a list of lists, or None."""
+    tot = (ctypes.c_double * (4 * ndomains))() if ndomains else None
+    _check(_lib.lbm_batch_moments(b, _ptr(rho), _ptr(s), tot))
+    return None if tot is None else [list(tot[4 * i:4 * i + 4]) for i in range(ndomains)]
+
+
+def lbm_batch_get_f64(b: int, out) -> None:
+    _check(_lib.lbm_batch_get_f64(b, _ptr(out)))
+
+
+def lbm_batch_time(b: int) -> int:
+    return int(_lib.lbm_batch_time(b))
+
+
+def lbm_batch_set_spin_limit(b: int, polls: int) -> None:
+    _check(_lib.lbm_batch_set_spin_limit(b, int(polls)))
+
+
+def lbm_batch_destroy(b: int) -> None:
+    _lib.lbm_batch_destroy(b)
+
+
 # ---- convenience wrapper: torch owns the buffers ---------------------------------------------
 
 class Simulation:
@@ -392,3 +544,89 @@ class Objective:
                 return gt, gu, gg, None
 
         return _Fn
+
+
+class Batch:
+    """A batch of independent domains plus the torch device buffers it runs on.
+
+    ``domains`` is a list of dicts (shape, tensor, tensor_kind, tau, rho [N_d], s [d][N_d]);
+    the initial state of each domain is f^eq(rho, s).
+    """
+
+    def __init__(self, lattice, storage, domains, order=3, shift="rest", rho0=1.0, device="cuda", stream=None):
+        import numpy as np
+        import torch
+
+        self.torch = torch
+        self.params = make_batch_params(lattice, storage, domains, order, shift, rho0)
+        self.ndomains = len(domains)
+        self.d = 2 if self.params.lattice == LBM_D2Q9 else 3
+        self.q = {LBM_D2Q9: 9, LBM_D3Q19: 19, LBM_D3Q27: 27}[self.params.lattice]
+        self.cells, self.offsets = lbm_batch_cells(self.params)
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.pop_bytes = lbm_batch_pop_bytes(self.params)
+        self.pop_a = torch.empty(self.pop_bytes, dtype=torch.uint8, device=self.device)
+        self.pop_b = torch.empty(self.pop_bytes, dtype=torch.uint8, device=self.device)
+        self.scratch = torch.empty(lbm_batch_scratch_bytes(self.params), dtype=torch.uint8, device=self.device)
+        rho = np.concatenate([np.asarray(dm["rho"], dtype=np.float64).reshape(-1) for dm in domains])
+        s = np.concatenate([np.asarray(dm["s"], dtype=np.float64).reshape(self.d, -1) for dm in domains], axis=1)
+        rho_t = torch.as_tensor(rho).to(self.device)
+        s_t = torch.as_tensor(np.ascontiguousarray(s)).to(self.device)
+        torch.cuda.synchronize(self.device)
+        self.b = lbm_batch_init(self.params, self.pop_a, self.pop_b, self.scratch, rho_t, s_t,
+                                self.stream.cuda_stream)
+
+    def close(self):
+        if getattr(self, "b", None):
+            lbm_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def t(self) -> int:
+        return lbm_batch_time(self.b)
+
+    def step(self, nsteps: int = 1):
+        lbm_batch_step(self.b, nsteps)
+        return self
+
+    def status(self):
+        lbm_batch_status(self.b)
+
+    def set_schedule(self, **kw):
+        lbm_batch_set_schedule(self.b, make_batch_schedule(**kw))
+
+    def schedule(self) -> dict:
+        return lbm_batch_get_schedule(self.b).as_dict()
+
+    def autotune(self, trial_steps: int = 20):
+        """Pick the fastest schedule by measurement; returns (schedule dict, ms per step)."""
+        backup = self.torch.empty(self.pop_bytes, dtype=self.torch.uint8, device=self.device)
+        s, ms = lbm_batch_autotune(self.b, backup, trial_steps)
+        del backup
+        return s.as_dict(), ms
+
+    def moments(self, fields: bool = True):
+        """(rho [C], s [d][C] device float64 tensors or None, totals [ndomains][4] list)."""
+        torch = self.torch
+        rho = torch.empty(self.cells, dtype=torch.float64, device=self.device) if fields else None
+        s = torch.empty((self.d, self.cells), dtype=torch.float64, device=self.device) if fields else None
+        tot = lbm_batch_moments(self.b, rho, s, self.ndomains)
+        return rho, s, tot
+
+    def f64(self):
+        """Canonical populations in FP64 as a device tensor [q * C]; domain i is the slice
+        [q * offsets[i], q * offsets[i + 1]) viewed as [q][N_i]."""
+        out = self.torch.empty(self.q * self.cells, dtype=self.torch.float64, device=self.device)
+        lbm_batch_get_f64(self.b, out)
+        return out
+
+    def domain_f64(self, full, i: int):
+        n = self.offsets[i + 1] - self.offsets[i]
+        return full[self.q * self.offsets[i]:self.q * self.offsets[i + 1]].reshape(self.q, n)

@@ -36,12 +36,24 @@ def build(verbose: bool = False) -> str:
     bdir = os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     os.makedirs(OUT_DIR, exist_ok=True)
-    kobj = os.path.join(bdir, "kernels.o")
-    hobj = os.path.join(bdir, "capi.o")
-    _run([hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, "kernels.hip"), "-o", kobj], verbose)
-    _run(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, "capi.cpp"), "-o", hobj], verbose)
+    jobs, objs = [], []
+    for name in sorted(os.listdir(CSRC)):
+        stem, ext = os.path.splitext(name)
+        if ext == ".hip":
+            cmd = [hipcc, *HIP_FLAGS, "-c", os.path.join(CSRC, name), "-o", os.path.join(bdir, stem + "_hip.o")]
+        elif ext == ".cpp":
+            cmd = ["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, name), "-o", os.path.join(bdir, stem + ".o")]
+        else:
+            continue
+        objs.append(cmd[-1])
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        jobs.append((cmd, subprocess.Popen(cmd)))
+    failed = [cmd for cmd, proc in jobs if proc.wait() != 0]
+    if failed:
+        raise RuntimeError("compilation failed: " + "; ".join(" ".join(c) for c in failed))
     tmp = OUT + ".tmp"
-    _run([hipcc, "-shared", f"--offload-arch={ARCH}", "-fPIC", "-o", tmp, kobj, hobj], verbose)
+    _run([hipcc, "-shared", f"--offload-arch={ARCH}", "-fPIC", "-o", tmp, *objs], verbose)
     os.replace(tmp, OUT)
     return OUT
 

@@ -12,10 +12,12 @@
 
 #include "../../include/lbm.h"
 #include "common.hpp"
+#include "host.hpp"
 
 using namespace lbm;
 
-namespace {
+namespace lbm {
+namespace host {
 
 thread_local std::string g_last_error;
 
@@ -35,16 +37,8 @@ int fail_hip(hipError_t e, const char *what)
     return fail(LBM_ERR_HIP, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
 }
 
-constexpr double kCs2 = 1.0 / 3.0;
-
 // ---- lattice tables in canonical order -------------------------------------------------
 
-struct LatticeTable {
-    int q, d, np;
-    int c[kMaxQ][3];
-    double w[kMaxQ];
-    int opp[kMaxQ];
-};
 
 template <int LAT> void fill_table(LatticeTable &t)
 {
@@ -138,12 +132,6 @@ double det_from_cholesky(int d, const double *l)
     return p * p;
 }
 
-struct Prepared {
-    lbm_derived dv;
-    LatticeTable lat;
-    int d, q, bytes;
-    uint32_t n;
-};
 
 int prepare(const lbm_params *p, Prepared &out)
 {
@@ -274,7 +262,13 @@ int64_t align256(int64_t b) { return (b + 255) / 256 * 256; }
 
 bool aligned256(const void *ptr) { return ((uintptr_t)ptr & 255u) == 0; }
 
-}  // namespace
+template StepConsts<float> consts_for<float>(const lbm_params &, const Prepared &);
+template StepConsts<double> consts_for<double>(const lbm_params &, const Prepared &);
+
+}  // namespace host
+}  // namespace lbm
+
+using namespace lbm::host;
 
 struct lbm_ctx {
     lbm_params p;

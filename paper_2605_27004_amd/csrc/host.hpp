@@ -1,0 +1,54 @@
+// host.hpp -- host-side helpers shared by the single-grid (capi.cpp) and batched (batch.cpp)
+// parts of the C ABI: error reporting, parameter preparation and per-step constants.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/lbm.h"
+#include "common.hpp"
+
+namespace lbm {
+namespace host {
+
+constexpr double kCs2 = 1.0 / 3.0;
+
+// Velocity set in the library's canonical order (rest, then +c / -c of each pair).
+struct LatticeTable {
+    int q, d, np;
+    int c[kMaxQ][3];
+    double w[kMaxQ];
+    int opp[kMaxQ];
+};
+
+// Validated parameters with everything derived from them on the host.
+struct Prepared {
+    lbm_derived dv;
+    LatticeTable lat;
+    int d, q, bytes;
+    uint32_t n;
+};
+
+// Message of the last failing call on this thread (lbm_last_error).
+extern thread_local std::string g_last_error;
+
+// Record a message for lbm_last_error and return `code`.
+int fail(int code, const char *fmt, ...);
+int fail_hip(hipError_t e, const char *what);
+
+bool table_of(int lattice, LatticeTable &t);
+int storage_bytes(int storage);
+
+// Validate p and derive A^-1, K, omega, r_i and the shift; LBM_OK or a negative code.
+int prepare(const lbm_params *p, Prepared &out);
+
+// Kernel constants of one parameter set in arithmetic precision C.
+template <typename C> StepConsts<C> consts_for(const lbm_params &p, const Prepared &pr);
+
+int64_t align256(int64_t b);
+bool aligned256(const void *ptr);
+
+}  // namespace host
+}  // namespace lbm

@@ -24,6 +24,7 @@
 // wrap is a per-lane offset select.
 #include <hip/hip_runtime.h>
 
+#include "cell.hpp"
 #include "common.hpp"
 
 // No implicit contraction: every fused multiply-add below is written out, so the rounding of
@@ -34,246 +35,7 @@
 namespace lbm {
 namespace {
 
-__device__ inline float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ inline double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
-
-// ---- storage conversions ---------------------------------------------------------------
-
-template <typename S> struct Conv;
-template <> struct Conv<double> {
-    using C = double;
-    __device__ static double ld(double v) { return v; }
-    __device__ static double st(double v) { return v; }
-};
-template <> struct Conv<float> {
-    using C = float;
-    __device__ static float ld(float v) { return v; }
-    __device__ static float st(float v) { return v; }
-};
-template <> struct Conv<_Float16> {
-    using C = float;
-    __device__ static float ld(_Float16 v) { return (float)v; }
-    __device__ static _Float16 st(float v) { return (_Float16)v; }  // round to nearest even
-};
-template <> struct Conv<__bf16> {
-    using C = float;
-    __device__ static float ld(__bf16 v) { return (float)v; }
-    __device__ static __bf16 st(float v) { return (__bf16)v; }  // round to nearest even
-};
-
-// ---- neighbourhood ---------------------------------------------------------------------
-
-// Offsets (in cells) from a cell to its periodic neighbours at coordinate -1 and +1 along
-// one axis.
-struct AxisOff {
-    int32_t m1, p1;
-};
-
-__device__ inline AxisOff axis_off(int32_t v, int32_t n, int32_t stride)
-{
-    AxisOff o;
-    o.m1 = (v == 0) ? (n - 1) * stride : -stride;
-    o.p1 = (v == n - 1) ? -(n - 1) * stride : stride;
-    return o;
-}
-
-// Offset to the cell x - c for one velocity component c in {-1, 0, 1} (a constant after
-// unrolling).
-__device__ inline int32_t back(const AxisOff &o, int c) { return c > 0 ? o.m1 : (c < 0 ? o.p1 : 0); }
-
-struct Cell {
-    uint32_t own;
-    AxisOff ox, oy, oz;
-};
-
-__device__ inline Cell cell_of(const Grid &g, int32_t x, int32_t y, int32_t z)
-{
-    Cell c;
-    c.own = (uint32_t)((z * g.ny + y) * g.nx + x);
-    c.ox = axis_off(x, g.nx, 1);
-    c.oy = axis_off(y, g.ny, g.nx);
-    c.oz = axis_off(z, g.nz, g.nx * g.ny);
-    return c;
-}
-
-template <int LAT> __device__ inline uint32_t src_plus(const Cell &c, int p)
-{
-    const PairRow v = Lattice<LAT>::pair(p);
-    return c.own + (uint32_t)(back(c.ox, v.cx) + back(c.oy, v.cy) + back(c.oz, v.cz));
-}
-
-template <int LAT> __device__ inline uint32_t src_minus(const Cell &c, int p)
-{
-    const PairRow v = Lattice<LAT>::pair(p);
-    return c.own + (uint32_t)(back(c.ox, -v.cx) + back(c.oy, -v.cy) + back(c.oz, -v.cz));
-}
-
-// Element `idx` of population plane i; plane bases are wave-uniform and the per-lane offset
-// stays a 32-bit byte offset (planes are < 4 GiB).
-template <typename S> __device__ inline const S *plane(const S *base, int i, uint32_t n)
-{
-    return base + (size_t)i * n;
-}
-template <typename S> __device__ inline S *plane(S *base, int i, uint32_t n) { return base + (size_t)i * n; }
-
-template <typename S> __device__ inline S ld_at(const S *p, uint32_t idx)
-{
-    return *reinterpret_cast<const S *>(reinterpret_cast<const char *>(p) + (uint32_t)(idx * (uint32_t)sizeof(S)));
-}
-template <typename S> __device__ inline void st_at(S *p, uint32_t idx, S v)
-{
-    *reinterpret_cast<S *>(reinterpret_cast<char *>(p) + (uint32_t)(idx * (uint32_t)sizeof(S))) = v;
-}
-// Streaming store of the step's output: it is not read again within the step, and keeping it
-// out of the caches leaves them to the x-boundary lines the pulls share (measured faster; the
-// loads themselves stay cached for that reason).
-template <typename S> __device__ inline void st_stream(S *p, uint32_t idx, S v)
-{
-    __builtin_nontemporal_store(v, reinterpret_cast<S *>(reinterpret_cast<char *>(p) + (uint32_t)(idx * (uint32_t)sizeof(S))));
-}
-
-// ---- the collision -----------------------------------------------------------------------
-
-// Equilibrium deviations g^eq = f^eq - sigma of every direction for one cell with density
-// rho = rho0 + drho and lattice velocity s: eqp[0] is the rest velocity, eqp[p+1] / eqm[p+1]
-// are the +c / -c members of pair p.
-template <int LAT, int ORDER, typename C>
-__device__ inline void equilibrium_pairs(const StepConsts<C> &k, C drho, C rho, C sx, C sy, C sz, C *eqp, C *eqm)
-{
-    using L = Lattice<LAT>;
-    const C usq = fmad(sx, sx, fmad(sy, sy, sz * sz));
-    const C ksx = fmad(k.k[0], sx, fmad(k.k[3], sy, k.k[4] * sz));
-    const C ksy = fmad(k.k[3], sx, fmad(k.k[1], sy, k.k[5] * sz));
-    const C ksz = fmad(k.k[4], sx, fmad(k.k[5], sy, k.k[2] * sz));
-    const C even0 = C(-1.5) * usq;
-    const C bq = C(-4.5) * usq;
-    eqp[0] = fmad(k.w[0] * rho, even0, fmad(k.rest[0], drho, k.eoff[0]));
-#pragma unroll
-    for (int p = 0; p < L::NP; ++p) {
-        const PairRow v = L::pair(p);
-        // u = c.s and kc = c.(K s) for c in {-1, 0, 1}^3
-        C u = C(0), kc = C(0);
-        if (v.cx > 0) { u += sx; kc += ksx; }
-        if (v.cx < 0) { u -= sx; kc -= ksx; }
-        if (v.cy > 0) { u += sy; kc += ksy; }
-        if (v.cy < 0) { u -= sy; kc -= ksy; }
-        if (v.cz > 0) { u += sz; kc += ksz; }
-        if (v.cz < 0) { u -= sz; kc -= ksz; }
-        const C u2 = u * u;
-        const C even = fmad(C(4.5), u2, even0);
-        C odd;
-        if constexpr (ORDER == 3) {
-            odd = fmad(u, fmad(C(4.5), u2, k.a[p + 1] + bq), C(-3) * kc);
-        } else {
-            odd = C(3) * u;
-        }
-        const C wr = k.w[p + 1] * rho;
-        const C base = fmad(k.rest[p + 1], drho, k.eoff[p + 1]);
-        eqp[p + 1] = fmad(wr, even + odd, base);
-        eqm[p + 1] = fmad(wr, even - odd, base);
-    }
-}
-
-template <int LAT, typename C> __device__ inline void moments_of(const C *gp, const C *gm, C &drho, C &jx, C &jy, C &jz)
-{
-    using L = Lattice<LAT>;
-    drho = gp[0];
-    jx = C(0);
-    jy = C(0);
-    jz = C(0);
-#pragma unroll
-    for (int p = 0; p < L::NP; ++p) {
-        const PairRow v = L::pair(p);
-        drho += gp[p + 1] + gm[p + 1];
-        const C dif = gp[p + 1] - gm[p + 1];
-        if (v.cx > 0) jx += dif;
-        if (v.cx < 0) jx -= dif;
-        if (v.cy > 0) jy += dif;
-        if (v.cy < 0) jy -= dif;
-        if (v.cz > 0) jz += dif;
-        if (v.cz < 0) jz -= dif;
-    }
-}
-
-// Single-precision closure of the equilibrium's conserved moments. The FP32 constants of
-// the equilibrium (w_i, the per-pair K terms) are rounded, and their rounding is the same in
-// every cell and every step, so the computed g^eq carries a tiny but systematic excess of
-// momentum (fl(1/18) alone is 7.5e-9 too large) that BGK injects into the flow each step.
-// Here the momentum of the computed g^eq is measured and its deficit against j is put on the
-// axis pairs (which carry no other correction), and the rest population takes the mass
-// balance, so sum_i g^eq_i = drho and sum_i g^eq_i c_i = j hold up to per-operation
-// rounding -- the discrete identities eq:a0discrete / eq:a1discrete require exactly that.
-template <int LAT, typename C>
-__device__ inline void close_moments(C *eqp, C *eqm, C drho, C jx, C jy, C jz)
-{
-    using L = Lattice<LAT>;
-    C mx = C(0), my = C(0), mz = C(0), mass = C(0);
-#pragma unroll
-    for (int p = 0; p < L::NP; ++p) {
-        const PairRow v = L::pair(p);
-        mass += eqp[p + 1] + eqm[p + 1];
-        const C dif = eqp[p + 1] - eqm[p + 1];
-        if (v.cx > 0) mx += dif;
-        if (v.cx < 0) mx -= dif;
-        if (v.cy > 0) my += dif;
-        if (v.cy < 0) my -= dif;
-        if (v.cz > 0) mz += dif;
-        if (v.cz < 0) mz -= dif;
-    }
-    static_assert(L::pair(0).cx == 1 && L::pair(1).cy == 1, "axis pairs come first");
-    const C hx = C(0.5) * (jx - mx);
-    const C hy = C(0.5) * (jy - my);
-    eqp[1] += hx;
-    eqm[1] -= hx;
-    eqp[2] += hy;
-    eqm[2] -= hy;
-    if constexpr (L::D == 3) {
-        static_assert(L::D == 2 || L::pair(2).cz == 1, "axis pairs come first");
-        const C hz = C(0.5) * (jz - mz);
-        eqp[3] += hz;
-        eqm[3] -= hz;
-    }
-    eqp[0] = drho - mass;
-}
-
-// One BGK collision of eq:LBE_BGK on the pre-collision deviations of a cell (rest in gp[0],
-// pair p in gp[p+1] / gm[p+1]); the arrays receive the post-collision deviations. With FORCE
-// and k.forced set, the body force is added by the exact-difference method:
-// g* += g^eq(rho, s + F/rho) - g^eq(rho, s).
-template <int LAT, int ORDER, bool FORCE, typename C>
-__device__ inline void collide_cell(const StepConsts<C> &k, C *gp, C *gm)
-{
-    constexpr int NP = Lattice<LAT>::NP;
-    C drho, jx, jy, jz;
-    moments_of<LAT>(gp, gm, drho, jx, jy, jz);
-    const C rho = k.rho0 + drho;
-    const C inv = C(1) / rho;
-    C eqp[NP + 1], eqm[NP + 1];
-    equilibrium_pairs<LAT, ORDER, C>(k, drho, rho, jx * inv, jy * inv, jz * inv, eqp, eqm);
-    if constexpr (sizeof(C) == 4) close_moments<LAT>(eqp, eqm, drho, jx, jy, jz);
-    gp[0] = fmad(k.omega, eqp[0] - gp[0], gp[0]);
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-        gp[p + 1] = fmad(k.omega, eqp[p + 1] - gp[p + 1], gp[p + 1]);
-        gm[p + 1] = fmad(k.omega, eqm[p + 1] - gm[p + 1], gm[p + 1]);
-    }
-    if constexpr (FORCE) {
-        if (k.forced) {
-            // both equilibria closed (in FP32) on their own momenta, j + F and j, so the
-            // increment carries exactly F and no mass
-            const C fjx = jx + k.force[0], fjy = jy + k.force[1], fjz = jz + k.force[2];
-            C fqp[NP + 1], fqm[NP + 1];
-            equilibrium_pairs<LAT, ORDER, C>(k, drho, rho, fjx * inv, fjy * inv, fjz * inv, fqp, fqm);
-            if constexpr (sizeof(C) == 4) close_moments<LAT>(fqp, fqm, drho, fjx, fjy, fjz);
-            gp[0] += fqp[0] - eqp[0];
-#pragma unroll
-            for (int p = 0; p < NP; ++p) {
-                gp[p + 1] += fqp[p + 1] - eqp[p + 1];
-                gm[p + 1] += fqm[p + 1] - eqm[p + 1];
-            }
-        }
-    }
-}
+using namespace cell;
 
 // ---- kernels -------------------------------------------------------------------------------
 
@@ -293,27 +55,6 @@ __device__ inline uint32_t tile_of(const TileMap &m, uint32_t b)
     const uint32_t q = m.nblocks / 8u, r = m.nblocks % 8u;
     const uint32_t xcd = b % 8u, local = b / 8u;
     return xcd < r ? xcd * (q + 1u) + local : r * (q + 1u) + (xcd - r) * q + local;
-}
-
-// Where the canonical pre-collision population i of a cell lives in the state: normally the
-// post-collision value of the upstream cell x - c_i (pull streaming); when that cell is solid,
-// the cell's own post-collision value of the opposite direction (halfway bounce-back). The
-// link word has bit i set in the second case.
-struct Slot {
-    int plane;
-    uint32_t idx;
-};
-
-template <int LAT> __device__ inline Slot slot_plus(const Cell &c, int p, uint32_t links)
-{
-    if (links >> (2 * p + 1) & 1u) return Slot{2 * p + 2, c.own};
-    return Slot{2 * p + 1, src_plus<LAT>(c, p)};
-}
-
-template <int LAT> __device__ inline Slot slot_minus(const Cell &c, int p, uint32_t links)
-{
-    if (links >> (2 * p + 2) & 1u) return Slot{2 * p + 1, c.own};
-    return Slot{2 * p + 2, src_minus<LAT>(c, p)};
 }
 
 // Step variants: kPlain (periodic fluid: q pulls, collision, q streaming stores per cell);

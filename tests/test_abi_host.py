@@ -189,3 +189,69 @@ def test_null_context_calls_fail_cleanly():
     assert lbm._lib.lbm_grad(None, ctypes.byref(spec), None, None, None, None, None) == lbm.LBM_ERR_ARG
     assert lbm._lib.lbm_grad_workspace_bytes(None, ctypes.byref(spec)) == lbm.LBM_ERR_ARG
     assert lbm._lib.lbm_stream_copy(None, None, 16, None) == lbm.LBM_ERR_ARG
+
+
+# ---- batches (host side) --------------------------------------------------------------------
+
+def _doms(n=5, seed=1):
+    rng = np.random.default_rng(seed)
+    return [dict(shape=tuple(int(v) for v in rng.integers(1, 30, 3)), tensor=W.random_theta(seed + i),
+                 tensor_kind="theta", tau=0.8) for i in range(n)]
+
+
+def test_batch_layout_queries():
+    doms = _doms()
+    p = lbm.make_batch_params("D3Q19", "f32", doms)
+    total, offs = lbm.lbm_batch_cells(p)
+    sizes = [int(np.prod(d["shape"])) for d in doms]
+    assert total == sum(sizes) and offs == list(np.concatenate([[0], np.cumsum(sizes)]))
+    # one population array: q planes per domain, each rounded up to 128 cells
+    assert lbm.lbm_batch_pop_bytes(p) == sum(19 * ((n + 127) // 128 * 128) * 4 for n in sizes)
+    assert lbm.lbm_batch_scratch_bytes(p) > 0
+    p16 = lbm.make_batch_params("D3Q19", "f16", doms)
+    assert lbm.lbm_batch_pop_bytes(p16) * 2 == lbm.lbm_batch_pop_bytes(p)
+
+
+def test_batch_rejects_bad_domains_with_their_index():
+    doms = _doms()
+    doms[3]["tau"] = 0.5
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.lbm_batch_cells(lbm.make_batch_params("D3Q19", "f32", doms))
+    assert e.value.code == lbm.LBM_ERR_TAU and "domain 3" in str(e.value)
+    doms = _doms()
+    doms[2]["tensor"] = -doms[2]["tensor"]
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.lbm_batch_pop_bytes(lbm.make_batch_params("D3Q19", "f32", doms))
+    assert e.value.code == lbm.LBM_ERR_NOT_SPD and "domain 2" in str(e.value)
+    doms = _doms()
+    doms[0]["shape"] = (4, 4, 3)
+    with pytest.raises(lbm.LBMError) as e:
+        lbm.lbm_batch_cells(lbm.make_batch_params("D2Q9", "f64", doms))
+    assert e.value.code == lbm.LBM_ERR_ARG
+    p = lbm.make_batch_params("D3Q19", "f32", _doms())
+    p.ndomains = 0
+    assert lbm._lib.lbm_batch_cells(ctypes.byref(p), None) == lbm.LBM_ERR_ARG
+
+
+def test_batch_init_rejects_before_any_device_work():
+    p = lbm.make_batch_params("D3Q19", "f32", _doms())
+    out = ctypes.c_void_p()
+    assert lbm._lib.lbm_batch_init(ctypes.byref(out), ctypes.byref(p), None, None, None, None, None,
+                                   None) == lbm.LBM_ERR_ARG
+    assert lbm._lib.lbm_batch_init(ctypes.byref(out), ctypes.byref(p), 256 + 8, 512, 768, 1024, 2048,
+                                   None) == lbm.LBM_ERR_ALIGN
+    assert out.value is None
+
+
+def test_batch_null_handle_calls_fail_cleanly():
+    s = lbm.lbm_batch_schedule()
+    assert lbm._lib.lbm_batch_step(None, 1) == lbm.LBM_ERR_ARG
+    assert lbm._lib.lbm_batch_status(None) == lbm.LBM_ERR_ARG
+    assert lbm._lib.lbm_batch_set_schedule(None, ctypes.byref(s)) == lbm.LBM_ERR_ARG
+    assert lbm._lib.lbm_batch_get_schedule(None, ctypes.byref(s)) == lbm.LBM_ERR_ARG
+    assert lbm._lib.lbm_batch_autotune(None, None, 1, None, None) == lbm.LBM_ERR_ARG
+    assert lbm._lib.lbm_batch_moments(None, None, None, None) == lbm.LBM_ERR_ARG
+    assert lbm._lib.lbm_batch_get_f64(None, None) == lbm.LBM_ERR_ARG
+    assert lbm._lib.lbm_batch_set_spin_limit(None, 5) == lbm.LBM_ERR_ARG
+    assert lbm._lib.lbm_batch_time(None) == -1
+    lbm._lib.lbm_batch_destroy(None)
