@@ -12,7 +12,8 @@ stream-and-collide pass over the whole grid. Prints ONE JSON line:
                (profiles/), null if the kernel source changed since they were taken
   cpu_baseline the FP64 oracle on the host cores, a bounded sample of the same workload
   variants     FP16 / BF16 shifted-deviation storage and FP64 storage of the same workload:
-               MLUPS, roofline fraction and the per-field error against the FP64 path
+               MLUPS, roofline fraction and the per-field error against the FP64 path; the
+               FP32 step with the second-order equilibrium (cost of the third-order term)
   adjoint      gradient workload (D2Q9 512^2 and D3Q19 128^3 channels with gray obstacles,
                2000 steps, checkpoints every 100, FP32): time of lbm_grad (forward + reverse
                sweep) over the time of the forward pass alone; adjoint_fwd_ratio = D3Q19's
@@ -110,8 +111,8 @@ def main():
     cells = wl.cells
     q = 19
 
-    def make(storage):
-        p = lbm.make_params(wl.lattice, storage, wl.shape, wl.tensor, wl.tensor_kind, wl.tau, 3)
+    def make(storage, order=3):
+        p = lbm.make_params(wl.lattice, storage, wl.shape, wl.tensor, wl.tensor_kind, wl.tau, order)
         return lbm.Simulation(p, wl.rho, wl.s)
 
     # ---- headline: FP32 storage ----
@@ -196,6 +197,13 @@ def main():
             variants[storage + ("_shifted" if storage != "f64" else "")] = v
         got = run_fields("f32", wl.steps)
         variants["f32_shifted"] = {"err_vs_f64_after_%d_steps" % wl.steps: field_errors(got, ref, wl.u0)}
+        # cost of the third-order term: the same FP32 step with the second-order equilibrium
+        s_ = make("f32", order=2)
+        n_ = min(args.steps, 500)
+        t_ = timed_steps(s_, n_, args.warmup, torch)
+        del s_
+        variants["f32_order2"] = {"MLUPS": round(cells * n_ / t_ / 1e6, 1),
+                                  "frac": round(2 * q * 4 * cells / (t_ / n_) / 1e9 / PEAK_GBPS, 4)}
         del got, ref
         torch.cuda.empty_cache()
         line["variants"] = variants
