@@ -17,11 +17,16 @@ stream-and-collide pass over the whole grid. Prints ONE JSON line:
   adjoint      gradient workload (D2Q9 512^2 and D3Q19 128^3 channels with gray obstacles,
                2000 steps, checkpoints every 100, FP32): time of lbm_grad (forward + reverse
                sweep) over the time of the forward pass alone; adjoint_fwd_ratio = D3Q19's
+  porous       D3Q27 porous medium (ellipsoid mask, porosity 0.6, halfway bounce-back, body
+               force 1e-6, tensor cs^2 diag(1.5, 1, 0.5), tau = 0.9), FP64 / FP32 / FP16 / BF16:
+               MLUPS, fraction of peak on the useful bytes (fluid cells' populations plus the
+               link words) and each precision's error against the FP64 path after 1000 steps
   batched      512 independent D3Q19 domains (edges 16..64, own tensor and tau each), FP32,
                500 steps: the autotuned schedule's MLUPS and fraction of the 8 TB/s peak, beside
                fixed step-per-launch and persistent schedules
 
-Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-variants] [--no-adjoint] [--no-batched]
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-variants] [--no-adjoint] [--no-batched] [--batched-steps N]
+                       [--no-porous] [--porous-n N]
 """
 import argparse
 import hashlib
@@ -36,7 +41,9 @@ sys.path.insert(0, ROOT)
 PEAK_GBPS = 8000.0  # MI355X HBM3E
 METRIC = "MLUPS & % of HBM peak, D3Q19 256^3 fp32 vs fp16-shifted; adjoint/fwd ratio"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_d3q19_f32_256.txt")
-KERNEL_SRC = os.path.join(ROOT, "paper_2605_27004_amd", "csrc", "kernels.hip")
+# the step kernel's source: the kernel file and the per-cell header it instantiates
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2605_27004_amd", "csrc", f)
+               for f in ("kernels.hip", "cell.hpp", "common.hpp", "lattice.hpp")]
 
 
 def parse():
@@ -49,13 +56,21 @@ def parse():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-porous", action="store_true")
+    ap.add_argument("--porous-n", type=int, default=512)
+    ap.add_argument("--batched-stepwise-only", action="store_true",
+                    help="batched block: time the step-per-launch schedule only (no autotune, no cooperative launch)")
+    ap.add_argument("--batched-steps", type=int, default=0, help="steps of the batched block (0: the workload's 500)")
     ap.add_argument("--cpu-steps", type=int, default=3)
     return ap.parse_args()
 
 
 def kernel_sha():
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_per_launch():
@@ -235,11 +250,52 @@ def main():
     else:
         line["adjoint_fwd_ratio"] = None
 
+    # ---- porous medium: walls, body force, reduced-precision storage ----
+    if not args.no_porous:
+        wl3 = W.config3(n=args.porous_n)
+        mask = torch.as_tensor(wl3.meta["mask"]).cuda()
+        fluid = int((wl3.meta["mask"] == 0).sum())
+        por = {"grid": list(wl3.shape), "solid_fraction": round(1 - fluid / wl3.cells, 4), "steps": wl3.steps}
+        ref3 = None
+        for storage, sz in (("f64", 8), ("f32", 4), ("f16", 2), ("bf16", 2)):
+            p3 = lbm.make_params("D3Q27", storage, wl3.shape, wl3.tensor, "theta", wl3.tau, force=wl3.meta["force"],
+                                 masked=True)
+            s3 = lbm.Simulation(p3, wl3.rho, wl3.s, mask=mask)
+            n3 = 50
+            t3 = timed_steps(s3, n3, 5, torch) / n3
+            useful = fluid * 2 * 27 * sz + wl3.cells * 4
+            rec = {"MLUPS": round(wl3.cells / t3 / 1e6, 1), "fluid_MLUPS": round(fluid / t3 / 1e6, 1),
+                   "frac": round(useful / t3 / 1e9 / PEAK_GBPS, 4), "ms_per_step": round(t3 * 1e3, 4)}
+            s3.step(wl3.steps - n3 - 5)
+            rho3, sv3, _ = s3.moments()
+            torch.cuda.synchronize()
+            if ref3 is None:
+                ref3 = (rho3, sv3)
+                rec["max_s"] = sv3.abs().max().item()
+            else:
+                fl = mask == 0
+                rec["err_vs_f64_after_%d_steps" % wl3.steps] = {
+                    "rho": ((rho3 - ref3[0])[fl].abs().max() / ref3[0][fl].abs().max()).item(),
+                    "s": ((sv3 - ref3[1]).abs().max() / ref3[1].abs().max()).item()}
+                del rho3, sv3
+            por[storage] = rec
+            s3.close()
+            del s3
+            torch.cuda.empty_cache()
+        del ref3, mask
+        torch.cuda.empty_cache()
+        line["porous"] = por
+
     # ---- batched small domains: one schedule picked by the autotuner ----
     if not args.no_batched:
         wl5 = W.config5()
+        if args.batched_steps > 0:
+            wl5.steps = args.batched_steps
         bt = lbm.Batch(wl5.lattice, "f32", wl5.domains)
-        chosen, tune_ms = bt.autotune(trial_steps=20)
+        if args.batched_stepwise_only:
+            chosen, tune_ms = bt.schedule(), float("nan")
+        else:
+            chosen, tune_ms = bt.autotune(trial_steps=20)
 
         def time_batch(steps):
             bt.step(5)
@@ -265,6 +321,8 @@ def main():
                  "persistent_groups": dict(mode="persistent", xcd_group=1, wg_per_cu=2, chunk_cells=4096,
                                            group_bytes=192 << 20)}
         for name, sch in fixed.items():
+            if args.batched_stepwise_only and sch["mode"] != "stepwise":
+                continue
             bt.set_schedule(**sch)
             res[name] = figures(time_batch(wl5.steps))
         bt.close()
