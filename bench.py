@@ -9,7 +9,9 @@ stream-and-collide pass over the whole grid. Prints ONE JSON line:
   roofline     the step kernel against the 8 TB/s HBM peak: achieved = algorithmic bytes per
                launch (2 q sizeof(float) = 152 B per cell) / mean kernel time from HIP events
                on the launch stream; traffic = HBM bytes per launch from rocprofv3 counters
-               (profiles/), null if the kernel source changed since they were taken
+               (profiles/), null if the kernel source changed since they were taken; beside
+               it the plain copy kernel's bandwidth and the time of free streaming with the
+               step's own loads and stores (its data-movement floor)
   cpu_baseline the FP64 oracle on the host cores, a bounded sample of the same workload
   variants     FP16 / BF16 shifted-deviation storage and FP64 storage of the same workload:
                MLUPS, roofline fraction and the per-field error against the FP64 path; the
@@ -138,6 +140,15 @@ def main():
     alg_bytes = 2 * q * 4 * cells
     achieved = alg_bytes / kernel_s / 1e9
     _, _, tot = sim.moments(fields=False)
+    # data-movement floor: the same loads and stores without the collision
+    sim.stream_floor(args.warmup)
+    torch.cuda.synchronize()
+    f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    f0.record(sim.stream)
+    sim.stream_floor(args.steps)
+    f1.record(sim.stream)
+    torch.cuda.synchronize()
+    floor_s = f0.elapsed_time(f1) / 1e3 / args.steps
     del sim
     torch.cuda.empty_cache()
 
@@ -180,7 +191,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_GBPS, 4), "traffic": traffic_per_launch(),
                      "algorithmic_bytes_per_launch": alg_bytes, "kernel": "k_step<D3Q19, float, order 3, plain>",
-                     "copy_kernel_GBps": round(copy_gbps, 1), "frac_of_copy": round(achieved / copy_gbps, 4)},
+                     "copy_kernel_GBps": round(copy_gbps, 1), "frac_of_copy": round(achieved / copy_gbps, 4),
+                     "stream_floor_us": round(floor_s * 1e6, 1), "frac_of_stream_floor": round(floor_s / kernel_s, 4)},
         "mass_total": tot[0],
     }
 

@@ -227,6 +227,12 @@ int64_t lbm_grad_workspace_bytes(const lbm_ctx *ctx, const lbm_grad_spec *spec);
 int lbm_grad(lbm_ctx *ctx, const lbm_grad_spec *spec, void *workspace, double *objective, double *dtensor,
              double *dtau, double *dmask);
 
+/* Measurement aid: nsteps passes of free streaming (every population moved along its velocity,
+ * no collision) with exactly the step kernel's loads and stores, work-group shape and launch.
+ * Its time is the data-movement floor of the step. It changes the state (lbm_time does not
+ * advance); periodic grids only (LBM_ERR_UNSUPPORTED with a mask or gray field). */
+int lbm_stream_floor(lbm_ctx *ctx, int64_t nsteps);
+
 /* Free a context (NULL is allowed). Does not touch the caller's buffers. */
 void lbm_destroy(lbm_ctx *ctx);
 

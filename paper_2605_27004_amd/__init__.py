@@ -113,6 +113,7 @@ def _bind(path: str):
         "lbm_scratch_bytes": (i64, [ctypes.POINTER(lbm_params)]),
         "lbm_init": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(lbm_params), vp, vp, vp, vp, vp, vp, vp]),
         "lbm_step": (ctypes.c_int, [vp, i64]),
+        "lbm_stream_floor": (ctypes.c_int, [vp, i64]),
         "lbm_moments": (ctypes.c_int, [vp, vp, vp, dp]),
         "lbm_get_populations": (ctypes.c_int, [vp, vp]),
         "lbm_set_populations": (ctypes.c_int, [vp, vp]),
@@ -243,6 +244,10 @@ def lbm_init(p: lbm_params, pop_a, pop_b, scratch, rho0, s0, mask=None, stream=N
 
 def lbm_step(ctx: int, nsteps: int) -> None:
     _check(_lib.lbm_step(ctx, int(nsteps)))
+
+
+def lbm_stream_floor(ctx: int, nsteps: int) -> None:
+    _check(_lib.lbm_stream_floor(ctx, nsteps))
 
 
 def lbm_moments(ctx: int, rho=None, s=None, want_totals: bool = True):
@@ -475,6 +480,11 @@ class Simulation:
 
     def set_launch(self, block_x: int, block_y: int, flags: int = 0):
         lbm_set_launch(self.ctx, block_x, block_y, flags)
+
+    def stream_floor(self, nsteps: int = 1):
+        """Free streaming with the step's memory traffic (measurement aid; changes the state)."""
+        lbm_stream_floor(self.ctx, nsteps)
+        return self
 
     def moments(self, fields: bool = True):
         """(rho [N], s [d][N], totals[4]) as torch float64 tensors on the device (fields=False

@@ -380,6 +380,21 @@ int lbm_init(lbm_ctx **out, const lbm_params *p, void *pop_a, void *pop_b, void 
     return LBM_OK;
 }
 
+int lbm_stream_floor(lbm_ctx *c, int64_t nsteps)
+{
+    if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
+    if (nsteps < 0) return fail(LBM_ERR_ARG, "nsteps must be >= 0");
+    if (c->links || c->gray) return fail(LBM_ERR_UNSUPPORTED, "the streaming floor is defined for periodic grids only");
+    for (int64_t s = 0; s < nsteps; ++s) {
+        hipError_t e = launch_step(c->p.lattice, c->p.storage, c->p.order, c->grid, c->k64, c->k32, nullptr, nullptr,
+                                   c->pop[c->cur], c->pop[c->cur ^ 1], c->block_x, c->block_y,
+                                   c->launch_flags | kLaunchStreamOnly, c->stream);
+        if (e != hipSuccess) return fail_hip(e, "streaming kernel launch");
+        c->cur ^= 1;
+    }
+    return LBM_OK;
+}
+
 int lbm_step(lbm_ctx *c, int64_t nsteps)
 {
     if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");

@@ -121,44 +121,72 @@ template <typename S> __device__ inline void st_stream(S *p, uint32_t idx, S v)
 
 // ---- the collision -----------------------------------------------------------------------
 
+// Per-cell quantities of the folded equilibrium that every velocity pair shares.
+template <typename C> struct EqCell {
+    C rho, drho, sx, sy, sz, ksx, ksy, ksz, even0, bq;
+};
+
+template <typename C>
+__device__ inline EqCell<C> eq_cell(const StepConsts<C> &k, C drho, C rho, C sx, C sy, C sz)
+{
+    EqCell<C> e;
+    e.rho = rho;
+    e.drho = drho;
+    e.sx = sx;
+    e.sy = sy;
+    e.sz = sz;
+    const C usq = fmad(sx, sx, fmad(sy, sy, sz * sz));
+    e.ksx = fmad(k.k[0], sx, fmad(k.k[3], sy, k.k[4] * sz));
+    e.ksy = fmad(k.k[3], sx, fmad(k.k[1], sy, k.k[5] * sz));
+    e.ksz = fmad(k.k[4], sx, fmad(k.k[5], sy, k.k[2] * sz));
+    e.even0 = C(-1.5) * usq;
+    e.bq = C(-4.5) * usq;
+    return e;
+}
+
+// g^eq of the rest velocity.
+template <typename C> __device__ inline C eq_rest(const StepConsts<C> &k, const EqCell<C> &e)
+{
+    return fmad(k.w[0] * e.rho, e.even0, fmad(k.rest[0], e.drho, k.eoff[0]));
+}
+
+// g^eq of the +c / -c members of pair p.
+template <int LAT, int ORDER, typename C>
+__device__ inline void eq_pair(const StepConsts<C> &k, const EqCell<C> &e, int p, C &ep, C &em)
+{
+    const PairRow v = Lattice<LAT>::pair(p);
+    // u = c.s and kc = c.(K s) for c in {-1, 0, 1}^3
+    C u = C(0), kc = C(0);
+    if (v.cx > 0) { u += e.sx; kc += e.ksx; }
+    if (v.cx < 0) { u -= e.sx; kc -= e.ksx; }
+    if (v.cy > 0) { u += e.sy; kc += e.ksy; }
+    if (v.cy < 0) { u -= e.sy; kc -= e.ksy; }
+    if (v.cz > 0) { u += e.sz; kc += e.ksz; }
+    if (v.cz < 0) { u -= e.sz; kc -= e.ksz; }
+    const C u2 = u * u;
+    const C even = fmad(C(4.5), u2, e.even0);
+    C odd;
+    if constexpr (ORDER == 3) {
+        odd = fmad(u, fmad(C(4.5), u2, k.a[p + 1] + e.bq), C(-3) * kc);
+    } else {
+        odd = C(3) * u;
+    }
+    const C wr = k.w[p + 1] * e.rho;
+    const C base = fmad(k.rest[p + 1], e.drho, k.eoff[p + 1]);
+    ep = fmad(wr, even + odd, base);
+    em = fmad(wr, even - odd, base);
+}
+
 // Equilibrium deviations g^eq = f^eq - sigma of every direction for one cell with density
 // rho = rho0 + drho and lattice velocity s: eqp[0] is the rest velocity, eqp[p+1] / eqm[p+1]
 // are the +c / -c members of pair p.
 template <int LAT, int ORDER, typename C>
 __device__ inline void equilibrium_pairs(const StepConsts<C> &k, C drho, C rho, C sx, C sy, C sz, C *eqp, C *eqm)
 {
-    using L = Lattice<LAT>;
-    const C usq = fmad(sx, sx, fmad(sy, sy, sz * sz));
-    const C ksx = fmad(k.k[0], sx, fmad(k.k[3], sy, k.k[4] * sz));
-    const C ksy = fmad(k.k[3], sx, fmad(k.k[1], sy, k.k[5] * sz));
-    const C ksz = fmad(k.k[4], sx, fmad(k.k[5], sy, k.k[2] * sz));
-    const C even0 = C(-1.5) * usq;
-    const C bq = C(-4.5) * usq;
-    eqp[0] = fmad(k.w[0] * rho, even0, fmad(k.rest[0], drho, k.eoff[0]));
+    const EqCell<C> e = eq_cell(k, drho, rho, sx, sy, sz);
+    eqp[0] = eq_rest(k, e);
 #pragma unroll
-    for (int p = 0; p < L::NP; ++p) {
-        const PairRow v = L::pair(p);
-        // u = c.s and kc = c.(K s) for c in {-1, 0, 1}^3
-        C u = C(0), kc = C(0);
-        if (v.cx > 0) { u += sx; kc += ksx; }
-        if (v.cx < 0) { u -= sx; kc -= ksx; }
-        if (v.cy > 0) { u += sy; kc += ksy; }
-        if (v.cy < 0) { u -= sy; kc -= ksy; }
-        if (v.cz > 0) { u += sz; kc += ksz; }
-        if (v.cz < 0) { u -= sz; kc -= ksz; }
-        const C u2 = u * u;
-        const C even = fmad(C(4.5), u2, even0);
-        C odd;
-        if constexpr (ORDER == 3) {
-            odd = fmad(u, fmad(C(4.5), u2, k.a[p + 1] + bq), C(-3) * kc);
-        } else {
-            odd = C(3) * u;
-        }
-        const C wr = k.w[p + 1] * rho;
-        const C base = fmad(k.rest[p + 1], drho, k.eoff[p + 1]);
-        eqp[p + 1] = fmad(wr, even + odd, base);
-        eqm[p + 1] = fmad(wr, even - odd, base);
-    }
+    for (int p = 0; p < Lattice<LAT>::NP; ++p) eq_pair<LAT, ORDER, C>(k, e, p, eqp[p + 1], eqm[p + 1]);
 }
 
 template <int LAT, typename C> __device__ inline void moments_of(const C *gp, const C *gm, C &drho, C &jx, C &jy, C &jz)

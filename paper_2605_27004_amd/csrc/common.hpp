@@ -52,6 +52,7 @@ hipError_t launch_init(int lattice, int storage, int order, const Grid &g, const
 
 // Launch flags of the step kernel (same values as LBM_LAUNCH_* in lbm.h).
 constexpr int kLaunchXcdSlabs = 1;  // XCD-contiguous tile order
+constexpr int kLaunchStreamOnly = 1 << 8;  // library-internal: pulls and stores only (no collision)
 
 // gray: per-cell gray fraction m (partial bounce-back) or null.
 hipError_t launch_step(int lattice, int storage, int order, const Grid &g, const StepConsts<double> &k64,

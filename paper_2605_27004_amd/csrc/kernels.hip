@@ -61,7 +61,9 @@ __device__ inline uint32_t tile_of(const TileMap &m, uint32_t b)
 // kLinks (link word per cell: solid cells write zeros, links to solid cells bounce back, plus
 // the body force); kGray (gray fraction m per cell: f* = (1 - m) f^BGK + m f_opp, plus the
 // body force).
-enum StepMode : int { kPlain = 0, kLinks = 1, kGray = 2 };
+// kStream: the kPlain pulls and stores without the collision (free streaming), a measurement
+// aid that moves exactly the step's bytes in the step's pattern.
+enum StepMode : int { kPlain = 0, kLinks = 1, kGray = 2, kStream = 3 };
 
 template <int LAT, typename S, int ORDER, int MODE>
 __global__ __launch_bounds__(256) void k_step(const S *__restrict__ src, S *__restrict__ dst, const Grid g,
@@ -330,10 +332,10 @@ __global__ __launch_bounds__(256) void k_copy(const u32x4 *__restrict__ src, u32
 // of f; the stored deviations differ from f by constants, which cancel in every difference.
 
 // A0, A_a and the K-sensitivity G (9 entries, K treated as a general matrix; add coef * G)
-// of sum_k nu_k f^eq_k(rho, s) for f^eq_k = rho r_k + w_k rho P'_k(s).
+// of sum_k nu_k f^eq_k(rho, s) for f^eq_k = rho r_k + w_k rho P'_k(s), nu_k = keep * mu_k.
 template <int LAT, int ORDER, typename C>
-__device__ inline void equilibrium_vjp(const StepConsts<C> &k, C rho, C sx, C sy, C sz, const C *nup, const C *num,
-                                       C &A0, C &Ax, C &Ay, C &Az, C coef, C *G)
+__device__ inline void equilibrium_vjp(const StepConsts<C> &k, C rho, C sx, C sy, C sz, const C *mup, const C *mum,
+                                       C keep, C &A0, C &Ax, C &Ay, C &Az, C coef, C *G)
 {
     using L = Lattice<LAT>;
     const C usq = fmad(sx, sx, fmad(sy, sy, sz * sz));
@@ -343,8 +345,9 @@ __device__ inline void equilibrium_vjp(const StepConsts<C> &k, C rho, C sx, C sy
     const C even0 = C(-1.5) * usq;
     const C bq = C(-4.5) * usq;
     // rest velocity: u = 0, P' = -1.5 |s|^2, dP'/ds = -3 s
-    const C phi0 = nup[0] * k.w[0];
-    A0 = nup[0] * fmad(k.w[0], even0, k.rest[0]);
+    const C nu0 = keep * mup[0];
+    const C phi0 = nu0 * k.w[0];
+    A0 = nu0 * fmad(k.w[0], even0, k.rest[0]);
     C S1[3] = {C(0), C(0), C(0)}, S3[3] = {C(0), C(0), C(0)};
     C S2 = C(3) * phi0;
     C T0 = phi0, U0 = C(0);
@@ -375,7 +378,7 @@ __device__ inline void equilibrium_vjp(const StepConsts<C> &k, C rho, C sx, C sy
             Bm = fmad(C(-9), u, C(3));
         }
         const C w = k.w[p + 1];
-        const C np_ = nup[p + 1], nm_ = num[p + 1];
+        const C np_ = keep * mup[p + 1], nm_ = keep * mum[p + 1];
         const C fp = np_ * w, fm = nm_ * w;
         A0 = fmad(np_, fmad(w, even + odd, k.rest[p + 1]), A0);
         A0 = fmad(nm_, fmad(w, even - odd, k.rest[p + 1]), A0);
@@ -499,7 +502,7 @@ __global__ __launch_bounds__(256) void k_seed(const S *__restrict__ src, typenam
 // One reverse step: lam_in = lam(t+1) (canonical), state = the buffer whose gather gives f(t);
 // writes lam_out = lam(t), adds d m per cell to dmask and the work-group's G / d tau sums to
 // gpart (in the same order every step, so the totals are reproducible).
-template <int LAT, typename S, int ORDER>
+template <int LAT, typename S, int ORDER, bool FORCED>
 __global__ __launch_bounds__(256) void k_adjoint(const S *__restrict__ state, const typename Conv<S>::C *__restrict__ lam_in,
                                                  typename Conv<S>::C *__restrict__ lam_out,
                                                  const float *__restrict__ gray, double *__restrict__ dmask,
@@ -509,7 +512,8 @@ __global__ __launch_bounds__(256) void k_adjoint(const S *__restrict__ state, co
     using L = Lattice<LAT>;
     using C = typename Conv<S>::C;
     constexpr int NP = L::NP;
-    __shared__ double red[kGradPartials][256];
+    constexpr int kWaves = 256 / 64;
+    __shared__ double red[kGradPartials][kWaves];
     const int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     const int32_t y = blockIdx.y * blockDim.y + threadIdx.y;
     const int32_t z = blockIdx.z;
@@ -531,8 +535,6 @@ __global__ __launch_bounds__(256) void k_adjoint(const S *__restrict__ state, co
         const C rho = k.rho0 + drho;
         const C inv = C(1) / rho;
         const C sx = jx * inv, sy = jy * inv, sz = jz * inv;
-        C eqp[NP + 1], eqm[NP + 1];
-        equilibrium_pairs<LAT, ORDER, C>(k, drho, rho, sx, sy, sz, eqp, eqm);
         // adjoint of the post-collision populations: mu_k(x) = lam_k(t+1, x + c_k)
         C mup[NP + 1], mum[NP + 1];
         mup[0] = ld_at(plane(lam_in, 0, g.n), c.own);
@@ -542,76 +544,84 @@ __global__ __launch_bounds__(256) void k_adjoint(const S *__restrict__ state, co
             mum[p + 1] = ld_at(plane(lam_in, 2 * p + 2, g.n), src_plus<LAT>(c, p));
         }
         const C mg = gray ? (C)gray[c.own] : C(0);
-        const C keep = C(1) - mg;
-        C nup[NP + 1], num[NP + 1];
-#pragma unroll
-        for (int p = 0; p <= NP; ++p) {
-            nup[p] = keep * mup[p];
-            num[p] = keep * mum[p];
-        }
+        const C keep = C(1) - mg;  // nu_k = keep * mu_k
         const C w = k.omega;
-        const C a = k.forced ? w - C(1) : w;
+        const C a = FORCED ? w - C(1) : w;
+        // first pass over the directions: the transposed equilibrium Jacobian (and G)
         C A0, Ax, Ay, Az;
-        equilibrium_vjp<LAT, ORDER, C>(k, rho, sx, sy, sz, nup, num, A0, Ax, Ay, Az, a, G);
+        equilibrium_vjp<LAT, ORDER, C>(k, rho, sx, sy, sz, mup, mum, keep, A0, Ax, Ay, Az, a, G);
         C base = a * (A0 - (Ax * sx + Ay * sy + Az * sz) * inv);
         C ax = a * Ax * inv, ay = a * Ay * inv, az = a * Az * inv;
-        // post-BGK values b (deviations) and d tau
-        C bp[NP + 1], bm[NP + 1];
-        bp[0] = fmad(w, eqp[0] - gp[0], gp[0]);
-        dtau = nup[0] * (eqp[0] - gp[0]);
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            bp[p + 1] = fmad(w, eqp[p + 1] - gp[p + 1], gp[p + 1]);
-            bm[p + 1] = fmad(w, eqm[p + 1] - gm[p + 1], gm[p + 1]);
-            dtau = fmad(nup[p + 1], eqp[p + 1] - gp[p + 1], dtau);
-            dtau = fmad(num[p + 1], eqm[p + 1] - gm[p + 1], dtau);
-        }
-        dtau *= -w * w;
-        if (k.forced) {
-            const C fjx = jx + k.force[0], fjy = jy + k.force[1], fjz = jz + k.force[2];
-            const C tx = fjx * inv, ty = fjy * inv, tz = fjz * inv;
-            C fqp[NP + 1], fqm[NP + 1];
-            equilibrium_pairs<LAT, ORDER, C>(k, drho, rho, tx, ty, tz, fqp, fqm);
-            bp[0] += fqp[0] - eqp[0];
-#pragma unroll
-            for (int p = 0; p < NP; ++p) {
-                bp[p + 1] += fqp[p + 1] - eqp[p + 1];
-                bm[p + 1] += fqm[p + 1] - eqm[p + 1];
-            }
+        C tx = C(0), ty = C(0), tz = C(0);
+        if constexpr (FORCED) {
+            tx = (jx + k.force[0]) * inv;
+            ty = (jy + k.force[1]) * inv;
+            tz = (jz + k.force[2]) * inv;
             C B0, Bx, By, Bz;
-            equilibrium_vjp<LAT, ORDER, C>(k, rho, tx, ty, tz, nup, num, B0, Bx, By, Bz, C(1), G);
+            equilibrium_vjp<LAT, ORDER, C>(k, rho, tx, ty, tz, mup, mum, keep, B0, Bx, By, Bz, C(1), G);
             base += B0 - (Bx * tx + By * ty + Bz * tz) * inv;
             ax += Bx * inv;
             ay += By * inv;
             az += Bz * inv;
         }
-        // lam(t) at x and the gray-fraction sensitivity
+        // second pass: per direction the equilibrium again (cheaper than holding it in
+        // registers), the post-BGK value b, d tau, d m and lam(t) at x
+        __builtin_amdgcn_sched_barrier(0);
+        const EqCell<C> e = eq_cell(k, drho, rho, sx, sy, sz);
+        const EqCell<C> ef = eq_cell(k, drho, rho, tx, ty, tz);
         const C om = C(1) - w;
-        C dm = mup[0] * (gp[0] - bp[0]);
-        st_at(plane(lam_out, 0, g.n), c.own, fmad(mg, mup[0], fmad(om, nup[0], base)));
+        C dm;
+        {
+            const C eq = eq_rest(k, e);
+            C b = fmad(w, eq - gp[0], gp[0]);
+            dtau = (keep * mup[0]) * (eq - gp[0]);
+            if constexpr (FORCED) b += eq_rest(k, ef) - eq;
+            dm = mup[0] * (gp[0] - b);
+            st_at(plane(lam_out, 0, g.n), c.own, fmad(mg, mup[0], fmad(om, keep * mup[0], base)));
+        }
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
+            C ep, em;
+            eq_pair<LAT, ORDER, C>(k, e, p, ep, em);
+            C bp = fmad(w, ep - gp[p + 1], gp[p + 1]);
+            C bm = fmad(w, em - gm[p + 1], gm[p + 1]);
+            dtau = fmad(keep * mup[p + 1], ep - gp[p + 1], dtau);
+            dtau = fmad(keep * mum[p + 1], em - gm[p + 1], dtau);
+            if constexpr (FORCED) {
+                C fp, fm;
+                eq_pair<LAT, ORDER, C>(k, ef, p, fp, fm);
+                bp += fp - ep;
+                bm += fm - em;
+            }
             const PairRow v = L::pair(p);
             const C vc = (C)v.cx * ax + (C)v.cy * ay + (C)v.cz * az;
-            st_at(plane(lam_out, 2 * p + 1, g.n), c.own, fmad(mg, mum[p + 1], fmad(om, nup[p + 1], base + vc)));
-            st_at(plane(lam_out, 2 * p + 2, g.n), c.own, fmad(mg, mup[p + 1], fmad(om, num[p + 1], base - vc)));
-            dm = fmad(mup[p + 1], gm[p + 1] - bp[p + 1], dm);
-            dm = fmad(mum[p + 1], gp[p + 1] - bm[p + 1], dm);
+            st_at(plane(lam_out, 2 * p + 1, g.n), c.own, fmad(mg, mum[p + 1], fmad(om, keep * mup[p + 1], base + vc)));
+            st_at(plane(lam_out, 2 * p + 2, g.n), c.own, fmad(mg, mup[p + 1], fmad(om, keep * mum[p + 1], base - vc)));
+            dm = fmad(mup[p + 1], gm[p + 1] - bp, dm);
+            dm = fmad(mum[p + 1], gp[p + 1] - bm, dm);
         }
+        dtau *= -w * w;
         if (dmask) dmask[c.own] += (double)dm;
     }
+    // work-group sums of G and d tau: within each wave by lane exchange, then across the waves
+    double v[kGradPartials];
 #pragma unroll
-    for (int e = 0; e < 9; ++e) red[e][tid] = (double)G[e];
-    red[9][tid] = (double)dtau;
+    for (int e = 0; e < 9; ++e) v[e] = (double)G[e];
+    v[9] = (double)dtau;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+        for (int e = 0; e < kGradPartials; ++e) v[e] += __shfl_xor(v[e], off, 64);
+    if ((tid & 63) == 0)
+#pragma unroll
+        for (int e = 0; e < kGradPartials; ++e) red[e][tid >> 6] = v[e];
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (tid < h)
-            for (int e = 0; e < kGradPartials; ++e) red[e][tid] += red[e][tid + h];
-        __syncthreads();
-    }
     if (tid < kGradPartials) {
+        double t = red[tid][0];
+#pragma unroll
+        for (int wv = 1; wv < kWaves; ++wv) t += red[tid][wv];
         const uint32_t b = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-        gpart[kGradPartials * (size_t)b + tid] += red[tid][0];
+        gpart[kGradPartials * (size_t)b + tid] += t;
     }
 }
 
@@ -718,11 +728,14 @@ hipError_t launch_step(int lattice, int storage, int order, const Grid &g, const
             m.nblocks = g3.x * g3.y * g3.z;
             m.xcd_slabs = (flags & kLaunchXcdSlabs) ? 1u : 0u;
             const dim3 grid(m.nblocks);
-            const int mode = gray ? kGray : ((links != nullptr || kc->forced) ? kLinks : kPlain);
+            const int mode = (flags & kLaunchStreamOnly) ? kStream
+                             : gray ? kGray : ((links != nullptr || kc->forced) ? kLinks : kPlain);
             const S *in = (const S *)src;
             S *out = (S *)dst;
 #define LBM_STEP(O, M) hipLaunchKernelGGL((k_step<LAT, S, O, M>), grid, block, 0, stream, in, out, g, *kc, m, links, gray)
-            if (order == 2) {
+            if (mode == kStream) {
+                LBM_STEP(3, kStream);
+            } else if (order == 2) {
                 if (mode == kGray) LBM_STEP(2, kGray);
                 else if (mode == kLinks) LBM_STEP(2, kLinks);
                 else LBM_STEP(2, kPlain);
@@ -813,12 +826,15 @@ hipError_t launch_adjoint(int lattice, int storage, int order, const Grid &g, co
             const StepConsts<C> *kc;
             if constexpr (sizeof(C) == 8) kc = &k64; else kc = &k32;
             const dim3 grid = cell_grid(g, kBlockX, kRedThreads / kBlockX), block(kBlockX, kRedThreads / kBlockX);
-            if (order == 2)
-                hipLaunchKernelGGL((k_adjoint<LAT, S, 2>), grid, block, 0, stream, (const S *)state, (const C *)lam_in,
-                                   (C *)lam_out, gray, dmask, gpart, g, *kc);
-            else
-                hipLaunchKernelGGL((k_adjoint<LAT, S, 3>), grid, block, 0, stream, (const S *)state, (const C *)lam_in,
-                                   (C *)lam_out, gray, dmask, gpart, g, *kc);
+#define LBM_ADJ(O, F)                                                                                            \
+    hipLaunchKernelGGL((k_adjoint<LAT, S, O, F>), grid, block, 0, stream, (const S *)state, (const C *)lam_in,     \
+                       (C *)lam_out, gray, dmask, gpart, g, *kc)
+            if (order == 2) {
+                if (kc->forced) LBM_ADJ(2, true); else LBM_ADJ(2, false);
+            } else {
+                if (kc->forced) LBM_ADJ(3, true); else LBM_ADJ(3, false);
+            }
+#undef LBM_ADJ
             return hipGetLastError();
         });
     });

@@ -244,3 +244,26 @@ def test_half_storage_error_is_bounded(storage, shift, bounds):
               reference="oracle", **{k: float(v) for k, v in e.items()}))
     for k in bounds:
         assert e[k] <= bounds[k], (k, e[k])
+
+
+@pytest.mark.parametrize("lattice,shape,storage", [("D3Q19", (13, 7, 5), "f32"), ("D2Q9", (9, 6, 1), "f64"),
+                                                   ("D3Q27", (5, 6, 7), "f16")])
+def test_stream_floor_is_free_streaming(lattice, shape, storage):
+    """The measurement kernel moves every canonical population along its velocity and nothing
+    else: f_i(x) becomes f_i(x - n c_i), bit for bit."""
+    wl = _random_wl(lattice, shape, seed=7)
+    p = lbm.make_params(lattice, storage, shape, wl.tensor, "theta", wl.tau)
+    sim = lbm.Simulation(p, wl.rho, wl.s)
+    sim.step(2)
+    before = sim.f64().cpu().numpy()
+    n = 3
+    sim.stream_floor(n)
+    after = sim.f64().cpu().numpy()
+    assert sim.t == 2
+    _, _, c, _, _ = lbm.lbm_lattice_info(lbm.LATTICES[lattice])
+    nx, ny, nz = shape
+    for i, ci in enumerate(c):
+        f = before[i].reshape(nz, ny, nx)
+        shifted = np.roll(f, shift=(n * ci[2], n * ci[1], n * ci[0]), axis=(0, 1, 2))
+        assert np.array_equal(after[i].reshape(nz, ny, nx), shifted), i
+    sim.close()
