@@ -51,8 +51,7 @@ extern "C" {
 #define LBM_ERR_HIP (-5)         /* a HIP runtime call failed (message has its string)   */
 #define LBM_ERR_UNSUPPORTED (-6) /* valid request this build does not implement          */
 #define LBM_ERR_NONFINITE (-7)   /* a conservation total is NaN or infinite              */
-#define LBM_ERR_SIZE (-8)        /* grid too large: < 2^31 cells and one population plane
-                                    < 4 GiB (< 2 GiB with LBM_FLAG_MASK)                  */
+#define LBM_ERR_SIZE (-8)        /* grid too large for the library's 32-bit cell indices */
 
 /* ---- enumerations --------------------------------------------------------------------- */
 #define LBM_D2Q9 0

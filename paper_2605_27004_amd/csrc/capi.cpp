@@ -161,9 +161,6 @@ int prepare(const lbm_params *p, Prepared &out)
     // 32-bit cell indices and 32-bit byte offsets inside each population plane
     if (nd >= 2147483648.0 || nd * out.bytes >= 4294967296.0)
         return fail(LBM_ERR_SIZE, "grid of %.0f cells exceeds the 2^31-cell / 4 GiB-per-plane limit", nd);
-    // the masked step addresses both planes of a velocity pair from the first one
-    if ((p->flags & LBM_FLAG_MASK) && 2.0 * nd * out.bytes >= 4294967296.0)
-        return fail(LBM_ERR_SIZE, "masked grid of %.0f cells exceeds the 2 GiB-per-plane limit", nd);
     out.n = (uint32_t)(p->nx * p->ny * p->nz);
     if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LBM_ERR_TAU, "tau must be > 1/2 (got %g)", p->tau);
     if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) return fail(LBM_ERR_ARG, "rho0 must be > 0 (got %g)", p->rho0);

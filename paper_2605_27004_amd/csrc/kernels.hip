@@ -95,14 +95,9 @@ __global__ __launch_bounds__(256) void k_step(const S *__restrict__ src, S *__re
             gp[0] = Conv<S>::ld(ld_at(plane(src, 0, g.n), c.own));
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
-                // Both members of pair p, pulled or bounced back, lie in planes 2p+1 and 2p+2:
-                // one wave-uniform base and a per-lane 32-bit offset below 2 planes (the
-                // masked grid is limited to 2 planes < 4 GiB) select the slot.
-                const S *pair = plane(src, 2 * p + 1, g.n);
-                const uint32_t op = (lk >> (2 * p + 1) & 1u) ? g.n + c.own : src_plus<LAT>(c, p);
-                const uint32_t om = (lk >> (2 * p + 2) & 1u) ? c.own : g.n + src_minus<LAT>(c, p);
-                gp[p + 1] = Conv<S>::ld(ld_at(pair, op));
-                gm[p + 1] = Conv<S>::ld(ld_at(pair, om));
+                const Slot sp = slot_plus<LAT>(c, p, lk), sm = slot_minus<LAT>(c, p, lk);
+                gp[p + 1] = Conv<S>::ld(ld_at(plane(src, sp.plane, g.n), sp.idx));
+                gm[p + 1] = Conv<S>::ld(ld_at(plane(src, sm.plane, g.n), sm.idx));
             }
             collide_cell<LAT, ORDER, true, C>(k, gp, gm);
         }
