@@ -141,3 +141,45 @@ def test_general_kernel_launch_shape_independent():
     ref = gpu_run(wl, "f32", 15)["f"]
     for block in [(64, 4, 0), (128, 2, lbm.LBM_LAUNCH_XCD_SLABS), (192, 1, 0)]:
         assert np.array_equal(ref, gpu_run(wl, "f32", 15, block=block)["f"]), block
+
+
+def test_config3_full_size_matches_oracle():
+    """The porous workload at its full 512^3 size, in the benchmark's launch configuration:
+    element-wise density and velocity against the oracle after 6 steps (the oracle's
+    whole-grid budget; force raised to 1e-4 as in the reduced test so that |s| stands above
+    FP64 round-off), for FP64 and FP32 storage; then mass conservation over the workload's
+    1000 steps on the GPU alone."""
+    wl = W.config3(n=512)
+    force = np.array([1e-4, 0.0, 0.0])
+    mask = wl.meta["mask"]
+    steps = 6
+    print(f"[full] porous 512^3: oracle {steps} steps", flush=True)
+    ainv = oracle.tensor_to_ainv(wl.tensor, "theta", 3)
+    f = oracle.init("D3Q27", wl.shape, ainv, wl.rho, wl.s, mask=mask)
+    oracle.steps("D3Q27", wl.shape, ainv, wl.tau, f, steps, mask=mask, force=force)
+    rho_or, s_or = oracle.moments("D3Q27", f, mask=mask, force=force)
+    del f
+    fluid = mask == 0
+    mask_t = torch.as_tensor(mask).cuda()
+    for storage in ("f64", "f32"):
+        p = lbm.make_params("D3Q27", storage, wl.shape, wl.tensor, "theta", wl.tau, force=force, masked=True)
+        sim = lbm.Simulation(p, wl.rho, wl.s, mask=mask_t)
+        _, _, tot0 = sim.moments(fields=False)
+        sim.step(steps)
+        rho, s, _ = sim.moments()
+        rho, s = rho.cpu().numpy(), s.cpu().numpy()
+        e_rho = np.abs(rho[fluid] - rho_or[fluid]).max() / np.abs(rho_or[fluid]).max()
+        e_s = np.abs(s - s_or).max() / np.abs(s_or).max()
+        del rho, s
+        sim.step(wl.steps - steps)
+        _, _, tot = sim.moments(fields=False)
+        drift = abs(tot[0] - tot0[0]) / tot0[0]
+        print(f"[full] porous 512^3 {storage}: e(rho)={e_rho:.2e} e(s)={e_s:.2e} mass drift over {wl.steps} "
+              f"steps {drift:.2e}", flush=True)
+        _log(dict(lattice="D3Q27", shape=list(wl.shape), storage=storage, steps=steps, case="config3_full",
+                  rho=float(e_rho), s=float(e_s), mass_drift=float(drift)))
+        assert e_rho <= TOL[storage] and e_s <= TOL[storage], (storage, e_rho, e_s)
+        assert drift <= (1e-12 if storage == "f64" else 1e-9), drift
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
