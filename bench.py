@@ -113,8 +113,8 @@ def field_errors(a, b, u0):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
-              "(multi-GPU slab decomposition is a design, not an implementation).", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: the library runs on "
+              "one GPU (the multi-GPU slab decomposition is described, not implemented).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

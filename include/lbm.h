@@ -49,7 +49,7 @@ extern "C" {
 #define LBM_ERR_TAU (-3)         /* tau <= 1/2: eta = rho cs^2 (tau - 1/2) must be > 0   */
 #define LBM_ERR_ALIGN (-4)       /* a device buffer is not 256-byte aligned              */
 #define LBM_ERR_HIP (-5)         /* a HIP runtime call failed (message has its string)   */
-#define LBM_ERR_UNSUPPORTED (-6) /* valid request this build does not implement          */
+#define LBM_ERR_UNSUPPORTED (-6) /* valid request the library does not implement        */
 #define LBM_ERR_NONFINITE (-7)   /* a conservation total is NaN or infinite              */
 #define LBM_ERR_SIZE (-8)        /* grid too large for the library's 32-bit cell indices */
 
