@@ -202,8 +202,9 @@ int lbm_set_launch(lbm_ctx *ctx, int32_t block_x, int32_t block_y, int32_t flags
  * with j = sum_i f_i c_i. The forward states are kept every checkpoint_every steps and each
  * segment is recomputed (bit-identically) before its reverse steps. The adjoint populations
  * use the arithmetic precision of the storage; the parameter sums are FP64.
- * Supported: LBM_TENSOR_THETA and LBM_TENSOR_A, no mask or LBM_FLAG_GRAY (binary masks and
- * LBM_TENSOR_ATILDE return LBM_ERR_UNSUPPORTED). */
+ * Supported: every tensor kind (for LBM_TENSOR_ATILDE the derivative includes the det
+ * normalisation), no mask or LBM_FLAG_GRAY (a binary mask returns LBM_ERR_UNSUPPORTED: halfway
+ * walls have no continuous parameter). */
 typedef struct lbm_grad_spec {
     int32_t objective;        /* 0 = outlet mass flux, 1 = kinetic energy                    */
     int32_t reserved;         /* must be 0                                                   */

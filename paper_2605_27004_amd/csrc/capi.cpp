@@ -492,8 +492,6 @@ int grad_layout(const lbm_ctx *c, const lbm_grad_spec *spec, GradLayout &l)
         return fail(LBM_ERR_ARG, "outlet_plane %lld outside 0..%lld", (long long)spec->outlet_plane,
                     (long long)(c->p.nx - 1));
     if (c->links) return fail(LBM_ERR_UNSUPPORTED, "gradients with a binary solid mask are not supported");
-    if (c->p.tensor_kind == LBM_TENSOR_ATILDE)
-        return fail(LBM_ERR_UNSUPPORTED, "gradients for LBM_TENSOR_ATILDE are not supported");
     const int64_t popb = (int64_t)c->pr.q * c->grid.n * c->pr.bytes;
     const int64_t lamb = (int64_t)c->pr.q * c->grid.n * (c->p.storage == LBM_F64 ? 8 : 4);
     const int64_t nb = moments_blocks(c->grid);
@@ -591,8 +589,11 @@ int lbm_grad(lbm_ctx *c, const lbm_grad_spec *spec, void *workspace, double *obj
         double D[9] = {0};  // dJ/dT as a general matrix
         if (c->p.tensor_kind == LBM_TENSOR_THETA) {
             for (int i = 0; i < 9; ++i) D[i] = G[i] / kCs2;  // K = T / cs^2 - I
-        } else {  // T = A, K = A^-1 - I: dJ/dA = -A^-1 G A^-1
-            const double *ai = c->pr.dv.ainv;
+        } else {
+            // T = A, K = A^-1 - I: dJ/dA = -A^-1 G A^-1. T = A~ with A^-1 = s A~^-1 and
+            // s = det(A~)^(1/d): dA^-1 = s [tr(A~^-1 dA~) A~^-1 / d - A~^-1 dA~ A~^-1], so
+            // dJ/dA~ = [tr(G^T A^-1) A^-1 / d - A^-1 G A^-1] / s (A^-1 is symmetric).
+            const double *ai = c->pr.dv.ainv;  // zero outside the d x d block
             double t[9] = {0};
             for (int a = 0; a < 3; ++a)
                 for (int b = 0; b < 3; ++b)
@@ -603,6 +604,17 @@ int lbm_grad(lbm_ctx *c, const lbm_grad_spec *spec, void *workspace, double *obj
                     for (int k2 = 0; k2 < 3; ++k2) v += t[a * 3 + k2] * ai[k2 * 3 + b];
                     D[a * 3 + b] = -v;
                 }
+            if (c->p.tensor_kind == LBM_TENSOR_ATILDE) {
+                const double *T = c->p.tensor;
+                const double det = d == 2 ? T[0] * T[4] - T[1] * T[3]
+                                          : T[0] * (T[4] * T[8] - T[5] * T[7]) - T[1] * (T[3] * T[8] - T[5] * T[6]) +
+                                                T[2] * (T[3] * T[7] - T[4] * T[6]);
+                const double sc = std::pow(det, 1.0 / d);
+                double tr = 0.0;
+                for (int i = 0; i < 9; ++i) tr += G[i] * ai[i];
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) D[a * 3 + b] = (D[a * 3 + b] + tr * ai[a * 3 + b] / d) / sc;
+            }
         }
         for (int a = 0; a < 3; ++a)
             for (int b = 0; b < 3; ++b) {

@@ -26,8 +26,10 @@ def _case(lattice, shape, kind="theta", force=(1e-4, -5e-5, 2e-5), seed=3):
     gray = rng.uniform(0.0, 0.3, n)
     gray[rng.uniform(size=n) < 0.1] = 1.0
     t = W.config1_theta() if d == 2 else W.random_theta(seed)
-    if kind == "A":
+    if kind in ("A", "Atilde"):
         t = W.pad3(np.linalg.inv(3.0 * t[:d, :d]))      # A with A^-1 = theta / cs^2
+        if kind == "Atilde":
+            t = 1.7 * t                                  # an unnormalised multiple of A
     return dict(lattice=lattice, shape=shape, d=d, rho=rho, s=s, gray=gray, tensor=t, kind=kind, tau=0.8,
                 force=None if force is None else np.array(force[:d]))
 
@@ -53,7 +55,8 @@ def _gpu(c, storage, steps, objective, plane, ckpt, tensor=None, tau=None, gray=
 
 
 CASES = [("D2Q9", (16, 12, 1), "theta", "kinetic_energy"), ("D2Q9", (16, 12, 1), "theta", "flux"),
-         ("D3Q19", (8, 6, 5), "A", "kinetic_energy"), ("D3Q27", (7, 6, 5), "theta", "flux")]
+         ("D3Q19", (8, 6, 5), "A", "kinetic_energy"), ("D3Q27", (7, 6, 5), "theta", "flux"),
+         ("D2Q9", (14, 9, 1), "Atilde", "flux"), ("D3Q19", (7, 6, 5), "Atilde", "kinetic_energy")]
 
 
 @pytest.mark.parametrize("lattice,shape,kind,objective", CASES)
