@@ -203,8 +203,8 @@ int lbm_set_launch(lbm_ctx *ctx, int32_t block_x, int32_t block_y, int32_t flags
  * segment is recomputed (bit-identically) before its reverse steps. The adjoint populations
  * use the arithmetic precision of the storage; the parameter sums are FP64.
  * Supported: every tensor kind (for LBM_TENSOR_ATILDE the derivative includes the det
- * normalisation), no mask or LBM_FLAG_GRAY (a binary mask returns LBM_ERR_UNSUPPORTED: halfway
- * walls have no continuous parameter). */
+ * normalisation) and every wall model: none, LBM_FLAG_GRAY, or LBM_FLAG_MASK (halfway
+ * bounce-back; the adjoint follows the same links). */
 typedef struct lbm_grad_spec {
     int32_t objective;        /* 0 = outlet mass flux, 1 = kinetic energy                    */
     int32_t reserved;         /* must be 0                                                   */
@@ -223,7 +223,10 @@ int64_t lbm_grad_workspace_bytes(const lbm_ctx *ctx, const lbm_grad_spec *spec);
  *   dtensor:   host out [9] (may be NULL): dJ/dT_ab for the tensor as given, one value per
  *              independent entry (T_ab and T_ba are one entry), written symmetrically.
  *   dtau:      host out (may be NULL): dJ/dtau.
- *   dmask:     device out FP64 [N] (may be NULL): dJ/dm per cell (zeros without a gray field).
+ *   dmask:     device out FP64 [N] (may be NULL): dJ/dm per cell for the gray fraction m of
+ *              the partial bounce-back blend. With a gray field it is the derivative at the
+ *              given m; otherwise at m = 0 on every fluid cell (the sensitivity to adding a
+ *              little gray there), and zero on solid cells.
  * Synchronises the stream before returning. */
 int lbm_grad(lbm_ctx *ctx, const lbm_grad_spec *spec, void *workspace, double *objective, double *dtensor,
              double *dtau, double *dmask);

@@ -189,15 +189,17 @@ def steps(name: str, shape, ainv, tau: float, f: np.ndarray, nsteps: int, order:
 
 
 def steps_gray(name: str, shape, ainv, tau: float, f: np.ndarray, nsteps: int, gray, order: int = 3,
-               force=None, nthreads: int = 0) -> np.ndarray:
-    """Like :func:`steps` with a gray mask m ([N], in [0, 1]): f* = (1 - m) f^BGK + m f_opp."""
+               force=None, nthreads: int = 0, mask=None) -> np.ndarray:
+    """Like :func:`steps` with a gray mask m ([N]): f* = (1 - m) f^BGK + m f_opp on fluid cells,
+    optionally together with a solid mask (halfway bounce-back at the solid cells)."""
     nx, ny, nz = _shape3(shape)
     d = dim(name)
     a = np.ascontiguousarray(np.asarray(ainv, dtype=np.float64)[:d, :d])
     gm = np.ascontiguousarray(np.asarray(gray, dtype=np.float64).reshape(nx * ny * nz))
     fp, _keep_f = _force_ptr(force, d)
+    mp, _keep_m = _mask_ptr(mask, nx * ny * nz)
     rc = _load().orc_steps_gray(LATTICES[name], int(order), nx, ny, nz, _ptr(a), float(tau), int(nsteps), _ptr(f),
-                                None, _ptr(gm), fp, int(nthreads))
+                                mp, _ptr(gm), fp, int(nthreads))
     if rc:
         raise RuntimeError(f"orc_steps_gray failed ({rc})")
     return f

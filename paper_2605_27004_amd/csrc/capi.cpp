@@ -491,7 +491,6 @@ int grad_layout(const lbm_ctx *c, const lbm_grad_spec *spec, GradLayout &l)
     if (spec->objective == 0 && (spec->outlet_plane < 0 || spec->outlet_plane >= c->p.nx))
         return fail(LBM_ERR_ARG, "outlet_plane %lld outside 0..%lld", (long long)spec->outlet_plane,
                     (long long)(c->p.nx - 1));
-    if (c->links) return fail(LBM_ERR_UNSUPPORTED, "gradients with a binary solid mask are not supported");
     const int64_t popb = (int64_t)c->pr.q * c->grid.n * c->pr.bytes;
     const int64_t lamb = (int64_t)c->pr.q * c->grid.n * (c->p.storage == LBM_F64 ? 8 : 4);
     const int64_t nb = moments_blocks(c->grid);
@@ -554,7 +553,7 @@ int lbm_grad(lbm_ctx *c, const lbm_grad_spec *spec, void *workspace, double *obj
     void *lam_in = ws + l.lam_a, *lam_out = ws + l.lam_b;
     double *gpart = (double *)(ws + l.gpart), *jpart = (double *)(ws + l.jpart), *sums = (double *)(ws + l.sums);
     e = launch_seed(c->p.lattice, c->p.storage, c->grid, c->k64, c->k32, c->pop[c->cur], lam_in, jpart,
-                    spec->objective, (int)spec->outlet_plane, st);
+                    spec->objective, (int)spec->outlet_plane, c->links, st);
     if (e == hipSuccess) e = launch_sum(jpart, nb, 1, sums, st);
     if (e == hipSuccess) e = launch_zero(gpart, (uint64_t)kGradPartialsHost * nb, st);
     if (e == hipSuccess && dmask) e = launch_zero(dmask, c->grid.n, st);
@@ -564,13 +563,13 @@ int lbm_grad(lbm_ctx *c, const lbm_grad_spec *spec, void *workspace, double *obj
         const int64_t len = std::min(spec->checkpoint_every, spec->nsteps - sgi * spec->checkpoint_every);
         auto state = [&](int64_t t) { return t == 0 ? ckpt(sgi) : segst(t); };
         for (int64_t t = 1; t < len; ++t) {
-            e = launch_step(c->p.lattice, c->p.storage, c->p.order, c->grid, c->k64, c->k32, nullptr, c->gray,
+            e = launch_step(c->p.lattice, c->p.storage, c->p.order, c->grid, c->k64, c->k32, c->links, c->gray,
                             state(t - 1), state(t), c->block_x, c->block_y, c->launch_flags, st);
             if (e != hipSuccess) return fail_hip(e, "segment recompute");
         }
         for (int64_t t = len - 1; t >= 0; --t) {
             e = launch_adjoint(c->p.lattice, c->p.storage, c->p.order, c->grid, c->k64, c->k32, state(t), lam_in,
-                               lam_out, c->gray, dmask, gpart, st);
+                               lam_out, c->gray, c->links, dmask, gpart, st);
             if (e != hipSuccess) return fail_hip(e, "adjoint step");
             std::swap(lam_in, lam_out);
         }

@@ -62,12 +62,13 @@ hipError_t launch_step(int lattice, int storage, int order, const Grid &g, const
 // ---- the gradient path (reverse sweep) ----
 constexpr int kGradPartialsHost = 10;  // per work-group: dJ/dK (9, general matrix), dJ/dtau
 // lam: adjoint populations [q][N] in the arithmetic precision of the storage.
+// links: the link words of a masked grid or null.
 hipError_t launch_seed(int lattice, int storage, const Grid &g, const StepConsts<double> &k64,
                        const StepConsts<float> &k32, const void *src, void *lam, double *jpart, int kind, int plane,
-                       hipStream_t stream);
+                       const uint32_t *links, hipStream_t stream);
 hipError_t launch_adjoint(int lattice, int storage, int order, const Grid &g, const StepConsts<double> &k64,
                           const StepConsts<float> &k32, const void *state, const void *lam_in, void *lam_out,
-                          const float *gray, double *dmask, double *gpart, hipStream_t stream);
+                          const float *gray, const uint32_t *links, double *dmask, double *gpart, hipStream_t stream);
 hipError_t launch_sum(const double *part, uint32_t nblocks, int m, double *out, hipStream_t stream);
 hipError_t launch_zero(double *p, uint64_t n, hipStream_t stream);
 

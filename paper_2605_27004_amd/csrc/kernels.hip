@@ -443,7 +443,8 @@ constexpr int kGradPartials = 10;  // G (9) and d tau, per work-group
 template <int LAT, typename S>
 __global__ __launch_bounds__(256) void k_seed(const S *__restrict__ src, typename Conv<S>::C *__restrict__ lam,
                                               double *__restrict__ jpart, const Grid g,
-                                              const StepConsts<typename Conv<S>::C> k, const int kind, const int plane_x)
+                                              const StepConsts<typename Conv<S>::C> k, const int kind, const int plane_x,
+                                              const uint32_t *__restrict__ links)
 {
     using L = Lattice<LAT>;
     using C = typename Conv<S>::C;
@@ -456,19 +457,23 @@ __global__ __launch_bounds__(256) void k_seed(const S *__restrict__ src, typenam
     double jv = 0.0;
     if (x < g.nx && y < g.ny) {
         const Cell c = cell_of(g, x, y, z);
+        const uint32_t lk = links ? links[c.own] : 0u;
         C gp[NP + 1], gm[NP + 1];
         gp[0] = Conv<S>::ld(ld_at(plane(src, 0, g.n), c.own));
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
-            gp[p + 1] = Conv<S>::ld(ld_at(plane(src, 2 * p + 1, g.n), src_plus<LAT>(c, p)));
-            gm[p + 1] = Conv<S>::ld(ld_at(plane(src, 2 * p + 2, g.n), src_minus<LAT>(c, p)));
+            const Slot sp = slot_plus<LAT>(c, p, lk), sm = slot_minus<LAT>(c, p, lk);
+            gp[p + 1] = Conv<S>::ld(ld_at(plane(src, sp.plane, g.n), sp.idx));
+            gm[p + 1] = Conv<S>::ld(ld_at(plane(src, sm.plane, g.n), sm.idx));
         }
         C drho, jx, jy, jz;
         moments_of<LAT>(gp, gm, drho, jx, jy, jz);
         const C rho = k.rho0 + drho;
         const C mx = jx + C(0.5) * k.force[0], my = jy + C(0.5) * k.force[1], mz = jz + C(0.5) * k.force[2];
         C base = C(0), ux = C(0), uy = C(0), uz = C(0);
-        if (kind == 0) {
+        if (lk & 1u) {
+            // a solid cell holds no fluid: it adds nothing to J (and its lam is never read)
+        } else if (kind == 0) {
             if (x == plane_x) {
                 ux = C(1);
                 jv = (double)mx;
@@ -499,14 +504,30 @@ __global__ __launch_bounds__(256) void k_seed(const S *__restrict__ src, typenam
     if (tid == 0) jpart[(blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = red[0];
 }
 
+// Where the adjoint of the post-collision population of direction +c (resp. -c) of pair p at x
+// is read from lam(t+1): the slot of x + c (resp. x - c) in the same direction, or -- when that
+// cell is solid and the population bounces back -- x's own slot of the opposite direction. The
+// link word's bit for direction i marks x - c_i solid, so x + c is bit 2p+2 and x - c bit 2p+1.
+template <int LAT> __device__ inline Slot adjoint_slot_plus(const Cell &c, int p, uint32_t links)
+{
+    if (links >> (2 * p + 2) & 1u) return Slot{2 * p + 2, c.own};
+    return Slot{2 * p + 1, src_minus<LAT>(c, p)};
+}
+
+template <int LAT> __device__ inline Slot adjoint_slot_minus(const Cell &c, int p, uint32_t links)
+{
+    if (links >> (2 * p + 1) & 1u) return Slot{2 * p + 1, c.own};
+    return Slot{2 * p + 2, src_plus<LAT>(c, p)};
+}
+
 // One reverse step: lam_in = lam(t+1) (canonical), state = the buffer whose gather gives f(t);
 // writes lam_out = lam(t), adds d m per cell to dmask and the work-group's G / d tau sums to
 // gpart (in the same order every step, so the totals are reproducible).
 template <int LAT, typename S, int ORDER, bool FORCED>
 __global__ __launch_bounds__(256) void k_adjoint(const S *__restrict__ state, const typename Conv<S>::C *__restrict__ lam_in,
                                                  typename Conv<S>::C *__restrict__ lam_out,
-                                                 const float *__restrict__ gray, double *__restrict__ dmask,
-                                                 double *__restrict__ gpart, const Grid g,
+                                                 const float *__restrict__ gray, const uint32_t *__restrict__ links,
+                                                 double *__restrict__ dmask, double *__restrict__ gpart, const Grid g,
                                                  const StepConsts<typename Conv<S>::C> k)
 {
     using L = Lattice<LAT>;
@@ -520,28 +541,37 @@ __global__ __launch_bounds__(256) void k_adjoint(const S *__restrict__ state, co
     const int tid = threadIdx.y * blockDim.x + threadIdx.x;
     C G[9] = {C(0), C(0), C(0), C(0), C(0), C(0), C(0), C(0), C(0)};
     C dtau = C(0);
-    if (x < g.nx && y < g.ny) {
-        const Cell c = cell_of(g, x, y, z);
-        // forward quantities at x
+    const bool inside = x < g.nx && y < g.ny;
+    const Cell c = cell_of(g, inside ? x : 0, inside ? y : 0, z);
+    const uint32_t lk = (inside && links) ? links[c.own] : 0u;
+    if (inside && (lk & 1u)) {
+        // a solid cell holds no state: its adjoint is zero and it adds no sensitivity
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) st_at(plane(lam_out, i, g.n), c.own, C(0));
+    } else if (inside) {
+        // forward quantities at x (the canonical gather, bounce-back slots included)
         C gp[NP + 1], gm[NP + 1];
         gp[0] = Conv<S>::ld(ld_at(plane(state, 0, g.n), c.own));
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
-            gp[p + 1] = Conv<S>::ld(ld_at(plane(state, 2 * p + 1, g.n), src_plus<LAT>(c, p)));
-            gm[p + 1] = Conv<S>::ld(ld_at(plane(state, 2 * p + 2, g.n), src_minus<LAT>(c, p)));
+            const Slot sp = slot_plus<LAT>(c, p, lk), sm = slot_minus<LAT>(c, p, lk);
+            gp[p + 1] = Conv<S>::ld(ld_at(plane(state, sp.plane, g.n), sp.idx));
+            gm[p + 1] = Conv<S>::ld(ld_at(plane(state, sm.plane, g.n), sm.idx));
         }
         C drho, jx, jy, jz;
         moments_of<LAT>(gp, gm, drho, jx, jy, jz);
         const C rho = k.rho0 + drho;
         const C inv = C(1) / rho;
         const C sx = jx * inv, sy = jy * inv, sz = jz * inv;
-        // adjoint of the post-collision populations: mu_k(x) = lam_k(t+1, x + c_k)
+        // adjoint of the post-collision populations: mu_k(x) = lam_k(t+1, x + c_k), or, when
+        // x + c_k is solid (halfway bounce-back), lam_opp(k)(t+1, x)
         C mup[NP + 1], mum[NP + 1];
         mup[0] = ld_at(plane(lam_in, 0, g.n), c.own);
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
-            mup[p + 1] = ld_at(plane(lam_in, 2 * p + 1, g.n), src_minus<LAT>(c, p));
-            mum[p + 1] = ld_at(plane(lam_in, 2 * p + 2, g.n), src_plus<LAT>(c, p));
+            const Slot ap = adjoint_slot_plus<LAT>(c, p, lk), am = adjoint_slot_minus<LAT>(c, p, lk);
+            mup[p + 1] = ld_at(plane(lam_in, ap.plane, g.n), ap.idx);
+            mum[p + 1] = ld_at(plane(lam_in, am.plane, g.n), am.idx);
         }
         const C mg = gray ? (C)gray[c.own] : C(0);
         const C keep = C(1) - mg;  // nu_k = keep * mu_k
@@ -797,7 +827,7 @@ hipError_t launch_permute(int lattice, int storage, int mode, const Grid &g, con
 
 hipError_t launch_seed(int lattice, int storage, const Grid &g, const StepConsts<double> &k64,
                        const StepConsts<float> &k32, const void *src, void *lam, double *jpart, int kind, int plane,
-                       hipStream_t stream)
+                       const uint32_t *links, hipStream_t stream)
 {
     return by_lattice(lattice, [&](auto lat) {
         return by_storage(storage, [&](auto sv) {
@@ -808,7 +838,7 @@ hipError_t launch_seed(int lattice, int storage, const Grid &g, const StepConsts
             if constexpr (sizeof(C) == 8) kc = &k64; else kc = &k32;
             const dim3 grid = cell_grid(g, kBlockX, kRedThreads / kBlockX), block(kBlockX, kRedThreads / kBlockX);
             hipLaunchKernelGGL((k_seed<LAT, S>), grid, block, 0, stream, (const S *)src, (C *)lam, jpart, g, *kc, kind,
-                               plane);
+                               plane, links);
             return hipGetLastError();
         });
     });
@@ -816,7 +846,7 @@ hipError_t launch_seed(int lattice, int storage, const Grid &g, const StepConsts
 
 hipError_t launch_adjoint(int lattice, int storage, int order, const Grid &g, const StepConsts<double> &k64,
                           const StepConsts<float> &k32, const void *state, const void *lam_in, void *lam_out,
-                          const float *gray, double *dmask, double *gpart, hipStream_t stream)
+                          const float *gray, const uint32_t *links, double *dmask, double *gpart, hipStream_t stream)
 {
     return by_lattice(lattice, [&](auto lat) {
         return by_storage(storage, [&](auto sv) {
@@ -828,7 +858,7 @@ hipError_t launch_adjoint(int lattice, int storage, int order, const Grid &g, co
             const dim3 grid = cell_grid(g, kBlockX, kRedThreads / kBlockX), block(kBlockX, kRedThreads / kBlockX);
 #define LBM_ADJ(O, F)                                                                                            \
     hipLaunchKernelGGL((k_adjoint<LAT, S, O, F>), grid, block, 0, stream, (const S *)state, (const C *)lam_in,     \
-                       (C *)lam_out, gray, dmask, gpart, g, *kc)
+                       (C *)lam_out, gray, links, dmask, gpart, g, *kc)
             if (order == 2) {
                 if (kc->forced) LBM_ADJ(2, true); else LBM_ADJ(2, false);
             } else {

@@ -96,3 +96,29 @@ def test_objectives_on_uniform_flow(name):
     ke = oracle.objective(name, shape, f, 1, force=F)
     j = 1.1 * s + F / 2
     assert ke == pytest.approx(int(np.prod(shape)) * 0.5 * (j @ j) / 1.1, rel=1e-13)
+
+
+@pytest.mark.parametrize("name", ["D2Q9", "D3Q19"])
+def test_gray_with_solid_mask(name):
+    """Gray cells and a solid mask together: a zero gray field is exactly the masked update,
+    and any gray field on the fluid cells still conserves mass."""
+    d = oracle.dim(name)
+    shape = (9, 7, 5 if d == 3 else 1)
+    n = int(np.prod(shape))
+    rng = np.random.default_rng(12)
+    mask = (rng.uniform(size=n) < 0.25).astype(np.uint8)
+    rho0, s0 = W.random_fields(shape, d, seed=13)
+    t = W.random_theta(2)[:d, :d] if d == 3 else W.config1_theta()[:2, :2]
+    ainv = oracle.tensor_to_ainv(t, "theta", d)
+    force = np.array([2e-5, -1e-5, 1e-5])[:d]
+    a = oracle.init(name, shape, ainv, rho0, s0, mask=mask)
+    b = a.copy()
+    oracle.steps(name, shape, ainv, 0.8, a, 40, mask=mask, force=force)
+    oracle.steps_gray(name, shape, ainv, 0.8, b, 40, np.zeros(n), mask=mask, force=force)
+    assert np.array_equal(a, b)
+    g = oracle.init(name, shape, ainv, rho0, s0, mask=mask)
+    m0 = g.sum()
+    gray = rng.uniform(0.0, 0.6, n) * (mask == 0)
+    oracle.steps_gray(name, shape, ainv, 0.8, g, 60, gray, mask=mask, force=force)
+    assert abs(g.sum() - m0) / m0 < 1e-13
+    assert np.all(g[:, mask == 1] == 0.0)
