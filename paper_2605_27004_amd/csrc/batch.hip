@@ -65,7 +65,7 @@ __device__ inline void step_cell(const S *__restrict__ src, S *__restrict__ dst,
         gp[p + 1] = Conv<S>::ld(ld_at(plane(src, 2 * p + 1, stride), src_plus<LAT>(c, p)));
         gm[p + 1] = Conv<S>::ld(ld_at(plane(src, 2 * p + 2, stride), src_minus<LAT>(c, p)));
     }
-    collide_cell<LAT, ORDER, false, C>(k, gp, gm);
+    collide_cell<LAT, ORDER, false, C, kClose<S>>(k, gp, gm);
     st_stream(plane(dst, 0, stride), c.own, Conv<S>::st(gp[0]));
 #pragma unroll
     for (int p = 0; p < NP; ++p) {

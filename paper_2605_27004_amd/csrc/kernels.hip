@@ -99,7 +99,7 @@ __global__ __launch_bounds__(256) void k_step(const S *__restrict__ src, S *__re
                 gp[p + 1] = Conv<S>::ld(ld_at(plane(src, sp.plane, g.n), sp.idx));
                 gm[p + 1] = Conv<S>::ld(ld_at(plane(src, sm.plane, g.n), sm.idx));
             }
-            collide_cell<LAT, ORDER, true, C>(k, gp, gm);
+            collide_cell<LAT, ORDER, true, C, kClose<S>>(k, gp, gm);
         }
     } else {
         gp[0] = Conv<S>::ld(ld_at(plane(src, 0, g.n), c.own));
@@ -110,7 +110,7 @@ __global__ __launch_bounds__(256) void k_step(const S *__restrict__ src, S *__re
         }
     }
 
-    if constexpr (MODE == kPlain) collide_cell<LAT, ORDER, false, C>(k, gp, gm);
+    if constexpr (MODE == kPlain) collide_cell<LAT, ORDER, false, C, kClose<S>>(k, gp, gm);
     if constexpr (MODE == kGray) {
         C pp[NP + 1], pm[NP + 1];
 #pragma unroll
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(256) void k_step(const S *__restrict__ src, S *__re
             pp[p] = gp[p];
             pm[p] = gm[p];
         }
-        collide_cell<LAT, ORDER, true, C>(k, gp, gm);
+        collide_cell<LAT, ORDER, true, C, kClose<S>>(k, gp, gm);
         // partial bounce-back on the node: the opposite of +c is -c of the same pair
         const C mg = (C)gray[c.own];
         gp[0] = fmad(mg, pp[0] - gp[0], gp[0]);
