@@ -215,3 +215,19 @@ def test_batched_workload_full_size():
                   **{k: float(v) for k, v in e.items()}))
         assert e["f"] <= TOL["f32"] and e["s"] <= TOL["f32"], (i, e)
     b.close()
+
+
+@pytest.mark.parametrize("sched", SCHEDULES, ids=lambda s: "-".join(f"{k}{v}" for k, v in s.items()))
+def test_single_domain_batch_equals_grid(sched):
+    """A batch of one domain (most of an XCD-placed order is padding; most persistent
+    work-groups have no item) is the single-grid run, bit for bit."""
+    doms = _small_batch(n=1, seed=30, edges=(20, 33))
+    doms[0]["shape"] = (37, 21, 9)
+    doms[0]["rho"], doms[0]["s"] = W.random_fields((37, 21, 9), 3, 31, amp_s=0.02)
+    b = lbm.Batch("D3Q19", "f32", doms)
+    b.set_schedule(**sched)
+    b.step(11)
+    b.status()
+    got = _batch_f(b, b.f64(), 0)
+    b.close()
+    assert np.array_equal(got, _single(doms[0], "D3Q19", "f32", 11))
