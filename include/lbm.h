@@ -311,6 +311,22 @@ typedef struct lbm_batch_schedule {
                             group through all steps before the next                            */
 } lbm_batch_schedule;
 
+/* One entry of a persistent schedule's work lists (lbm_batch_plan). */
+typedef struct lbm_batch_item {
+    int64_t domain;     /* domain index                                                    */
+    int64_t first_cell; /* first cell of the run within the domain (a multiple of 256)     */
+    int64_t cells;      /* cells in the run                                                */
+    int64_t group;      /* group of domains the run belongs to (groups run one after another) */
+    int64_t work_group; /* work-group that runs it; flat work-group w runs on XCD w mod 8   */
+} lbm_batch_item;
+
+/* Host only, no device work: the work lists the persistent schedule s would use on a device
+ * with cu_count compute units. Writes min(count, cap) items (items may be NULL if cap is 0),
+ * in the order each work-group runs them, and returns the count, or a negative LBM_ERR_*.
+ * Every cell of every domain is in exactly one item of each step. */
+int64_t lbm_batch_plan(const lbm_batch_params *p, const lbm_batch_schedule *s, int32_t cu_count,
+                       lbm_batch_item *items, int64_t cap);
+
 /* Build and upload the work lists of a schedule (synchronises the stream). */
 int lbm_batch_set_schedule(lbm_batch *b, const lbm_batch_schedule *s);
 int lbm_batch_get_schedule(const lbm_batch *b, lbm_batch_schedule *s);

@@ -88,6 +88,11 @@ class lbm_batch_schedule(ctypes.Structure):
 LBM_BATCH_STEPWISE, LBM_BATCH_PERSISTENT = 0, 1
 
 
+class lbm_batch_item(ctypes.Structure):
+    _fields_ = [("domain", ctypes.c_int64), ("first_cell", ctypes.c_int64), ("cells", ctypes.c_int64),
+                ("group", ctypes.c_int64), ("work_group", ctypes.c_int64)]
+
+
 class LBMError(RuntimeError):
     def __init__(self, code: int, message: str):
         super().__init__(f"[{code}] {message}")
@@ -140,6 +145,8 @@ def _bind(path: str):
         "lbm_batch_time": (i64, [vp]),
         "lbm_batch_set_spin_limit": (ctypes.c_int, [vp, ctypes.c_uint32]),
         "lbm_batch_destroy": (None, [vp]),
+        "lbm_batch_plan": (i64, [ctypes.POINTER(lbm_batch_params), ctypes.POINTER(lbm_batch_schedule), i32,
+                                 ctypes.POINTER(lbm_batch_item), i64]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -418,6 +425,19 @@ def lbm_batch_time(b: int) -> int:
 
 def lbm_batch_set_spin_limit(b: int, polls: int) -> None:
     _check(_lib.lbm_batch_set_spin_limit(b, int(polls)))
+
+
+def lbm_batch_plan(p: lbm_batch_params, s: lbm_batch_schedule, cu_count: int):
+    """Work lists of a persistent schedule (host only): a list of dicts with domain,
+    first_cell, cells, group and work_group, in the order each work-group runs them."""
+    n = _lib.lbm_batch_plan(ctypes.byref(p), ctypes.byref(s), int(cu_count), None, 0)
+    if n < 0:
+        _check(int(n))
+    arr = (lbm_batch_item * max(int(n), 1))()
+    n = _lib.lbm_batch_plan(ctypes.byref(p), ctypes.byref(s), int(cu_count), arr, int(n))
+    if n < 0:
+        _check(int(n))
+    return [{f: getattr(arr[i], f) for f, _ in lbm_batch_item._fields_} for i in range(int(n))]
 
 
 def lbm_batch_destroy(b: int) -> None:

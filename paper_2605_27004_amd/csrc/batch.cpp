@@ -234,10 +234,28 @@ void build_launch_order(lbm_batch *b, bool xcd)
     b->nlaunch = (uint32_t)b->launch.size();
 }
 
-int build_persistent(lbm_batch *b, const lbm_batch_schedule &s)
+// Work lists of the persistent schedule: items in the order each work-group runs them.
+struct PersistPlan {
+    std::vector<BatchItem> items;
+    std::vector<uint32_t> item_wg;   // work-group of each item
+    std::vector<uint32_t> wg_first;  // [nwg + 1] item ranges per work-group
+    std::vector<uint32_t> chunks;    // items per domain and step
+    uint32_t nwg = 0, max_chunks = 1;
+};
+
+int check_persistent(const lbm_batch_schedule &s)
 {
-    const Plan &pl = b->pl;
-    const int64_t nwg = (int64_t)s.wg_per_cu * b->cu_count;
+    if (s.chunk_cells < kTileCells || s.chunk_cells % kTileCells != 0)
+        return fail(LBM_ERR_ARG, "chunk_cells must be a positive multiple of %d (got %lld)", kTileCells,
+                    (long long)s.chunk_cells);
+    if (s.group_bytes < 0) return fail(LBM_ERR_ARG, "group_bytes must be >= 0");
+    if (s.wg_per_cu < 1) return fail(LBM_ERR_ARG, "wg_per_cu must be >= 1 (got %d)", s.wg_per_cu);
+    return LBM_OK;
+}
+
+int plan_persistent(const Plan &pl, const lbm_batch_schedule &s, int cu_count, PersistPlan &out)
+{
+    const int64_t nwg = (int64_t)s.wg_per_cu * cu_count;
     if (nwg > kMaxWorkGroups) return fail(LBM_ERR_ARG, "%lld work-groups exceed the limit %lld", (long long)nwg,
                                           (long long)kMaxWorkGroups);
     // groups of consecutive domains within the byte budget
@@ -257,7 +275,7 @@ int build_persistent(lbm_batch *b, const lbm_batch_schedule &s)
         int wg;
     };
     std::vector<Job> jobs;
-    b->chunks.assign(pl.dom.size(), 0u);
+    out.chunks.assign(pl.dom.size(), 0u);
     for (size_t g = 0; g < groups.size(); ++g) {
         // split each domain into near-equal runs of whole tiles, at most chunk_cells each
         std::vector<BatchItem> its;
@@ -274,7 +292,7 @@ int build_persistent(lbm_batch *b, const lbm_batch_schedule &s)
                 its.push_back(BatchItem{(uint32_t)d, (uint32_t)c0, (uint32_t)(c1 - c0), (uint32_t)g});
                 home.push_back(s.xcd_group ? x[gi] : -1);
             }
-            b->chunks[d] = (uint32_t)parts;
+            out.chunks[d] = (uint32_t)parts;
         }
         if (s.xcd_group) {
             // per XCD: its items over its own work-groups (w = k mod 8)
@@ -303,16 +321,31 @@ int build_persistent(lbm_batch *b, const lbm_batch_schedule &s)
         if (a.item.dom != c.item.dom) return a.item.dom < c.item.dom;
         return a.item.first < c.item.first;
     });
-    b->items.clear();
-    b->wg_first.assign((size_t)nwg + 1, 0u);
+    out.items.clear();
+    out.item_wg.clear();
+    out.wg_first.assign((size_t)nwg + 1, 0u);
     for (const Job &j : jobs) {
-        b->items.push_back(j.item);
-        ++b->wg_first[(size_t)j.wg + 1];
+        out.items.push_back(j.item);
+        out.item_wg.push_back((uint32_t)j.wg);
+        ++out.wg_first[(size_t)j.wg + 1];
     }
-    for (int64_t w = 0; w < nwg; ++w) b->wg_first[(size_t)w + 1] += b->wg_first[(size_t)w];
-    b->nwg = (uint32_t)nwg;
-    b->max_chunks = 1;
-    for (uint32_t c : b->chunks) b->max_chunks = std::max(b->max_chunks, c);
+    for (int64_t w = 0; w < nwg; ++w) out.wg_first[(size_t)w + 1] += out.wg_first[(size_t)w];
+    out.nwg = (uint32_t)nwg;
+    out.max_chunks = 1;
+    for (uint32_t c : out.chunks) out.max_chunks = std::max(out.max_chunks, c);
+    return LBM_OK;
+}
+
+int build_persistent(lbm_batch *b, const lbm_batch_schedule &s)
+{
+    PersistPlan pp;
+    const int rc = plan_persistent(b->pl, s, b->cu_count, pp);
+    if (rc) return rc;
+    b->items = std::move(pp.items);
+    b->wg_first = std::move(pp.wg_first);
+    b->chunks = std::move(pp.chunks);
+    b->nwg = pp.nwg;
+    b->max_chunks = pp.max_chunks;
     return LBM_OK;
 }
 
@@ -327,16 +360,14 @@ int apply_schedule(lbm_batch *b, const lbm_batch_schedule &s)
         int rc = upload(b, b->dlaunch, b->launch.data(), b->launch.size() * sizeof(TileRec));
         if (rc) return rc;
     } else {
-        if (s.chunk_cells < kTileCells || s.chunk_cells % kTileCells != 0)
-            return fail(LBM_ERR_ARG, "chunk_cells must be a positive multiple of %d (got %lld)", kTileCells,
-                        (long long)s.chunk_cells);
-        if (s.group_bytes < 0) return fail(LBM_ERR_ARG, "group_bytes must be >= 0");
+        int rc = check_persistent(s);
+        if (rc) return rc;
         int occ = 0;
         hipError_t e = batch_persist_occupancy(b->pl.lattice, b->pl.storage, b->pl.order, &occ);
         if (e != hipSuccess) return fail_hip(e, "hipOccupancyMaxActiveBlocksPerMultiprocessor");
         if (s.wg_per_cu < 1 || s.wg_per_cu > occ)
             return fail(LBM_ERR_ARG, "wg_per_cu must be in 1 .. %d for this kernel (got %d)", occ, s.wg_per_cu);
-        int rc = build_persistent(b, s);
+        rc = build_persistent(b, s);
         if (rc) return rc;
         rc = upload(b, b->ditems, b->items.data(), b->items.size() * sizeof(BatchItem));
         if (!rc) rc = upload(b, b->dwg_first, b->wg_first.data(), b->wg_first.size() * sizeof(uint32_t));
@@ -420,6 +451,34 @@ int64_t lbm_batch_cells(const lbm_batch_params *p, int64_t *offsets)
         offsets[pl.dom.size()] = pl.cells;
     }
     return pl.cells;
+}
+
+int64_t lbm_batch_plan(const lbm_batch_params *p, const lbm_batch_schedule *s, int32_t cu_count,
+                       lbm_batch_item *items, int64_t cap)
+{
+    if (!s) return fail(LBM_ERR_ARG, "schedule is NULL");
+    if (s->mode != LBM_BATCH_PERSISTENT) return fail(LBM_ERR_ARG, "only persistent schedules have work lists");
+    if (s->reserved != 0 || (s->xcd_group != 0 && s->xcd_group != 1)) return fail(LBM_ERR_ARG, "invalid schedule");
+    if (cu_count < 1) return fail(LBM_ERR_ARG, "cu_count must be >= 1");
+    if (cap < 0 || (cap > 0 && !items)) return fail(LBM_ERR_ARG, "items must hold cap entries");
+    int rc = check_persistent(*s);
+    if (rc) return rc;
+    Plan pl;
+    rc = plan_of(p, pl);
+    if (rc) return rc;
+    PersistPlan pp;
+    rc = plan_persistent(pl, *s, cu_count, pp);
+    if (rc) return rc;
+    const int64_t n = (int64_t)pp.items.size();
+    for (int64_t i = 0; i < std::min(n, cap); ++i) {
+        const BatchItem &it = pp.items[(size_t)i];
+        items[i].domain = it.dom;
+        items[i].first_cell = it.first;
+        items[i].cells = it.count;
+        items[i].group = it.group;
+        items[i].work_group = pp.item_wg[(size_t)i];
+    }
+    return n;
 }
 
 int64_t lbm_batch_pop_bytes(const lbm_batch_params *p)

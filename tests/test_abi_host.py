@@ -255,3 +255,58 @@ def test_batch_null_handle_calls_fail_cleanly():
     assert lbm._lib.lbm_batch_set_spin_limit(None, 5) == lbm.LBM_ERR_ARG
     assert lbm._lib.lbm_batch_time(None) == -1
     lbm._lib.lbm_batch_destroy(None)
+
+
+@pytest.mark.parametrize("xcd,group_bytes", [(1, 0), (0, 0), (1, 48 << 20)])
+def test_batch_persistent_plan(xcd, group_bytes):
+    """The persistent schedule's work lists (host only): every cell of every domain is in
+    exactly one item, items are runs of whole tiles, an XCD-placed plan keeps each domain on
+    one XCD, each work-group runs its items group by group, and the per-work-group load of each
+    group is within one item of the longest-processing-time bound."""
+    wl = W.config5(ndomains=64)
+    p = lbm.make_batch_params("D3Q19", "f32", wl.domains)
+    s = lbm.make_batch_schedule("persistent", xcd, 2, 16384, group_bytes)
+    cu = 256
+    items = lbm.lbm_batch_plan(p, s, cu)
+    sizes = [int(np.prod(d["shape"])) for d in wl.domains]
+    cover = {i: [] for i in range(len(sizes))}
+    for it in items:
+        assert it["first_cell"] % 256 == 0 and 0 < it["cells"] <= 16384
+        assert 0 <= it["work_group"] < 2 * cu
+        cover[it["domain"]].append((it["first_cell"], it["cells"]))
+    for d, runs in cover.items():
+        runs.sort()
+        pos = 0
+        for first, cells in runs:
+            assert first == pos
+            pos += cells
+        assert pos == sizes[d]
+    if xcd:
+        for d in cover:
+            assert len({it["work_group"] % 8 for it in items if it["domain"] == d}) == 1
+    last = {}
+    for it in items:   # per work-group, groups never go backwards
+        assert it["group"] >= last.get(it["work_group"], 0)
+        last[it["work_group"]] = it["group"]
+    for g in {it["group"] for it in items}:
+        git = [it for it in items if it["group"] == g]
+        load = {}
+        for it in git:
+            load[it["work_group"]] = load.get(it["work_group"], 0) + it["cells"]
+        biggest = max(it["cells"] for it in git)
+        total = sum(it["cells"] for it in git)
+        bins = 2 * cu if not xcd else 2 * cu // 8
+        per_bin_bound = (total / bins if not xcd else max(
+            sum(it["cells"] for it in git if it["work_group"] % 8 == k) for k in range(8)) / bins) + biggest
+        assert max(load.values()) <= per_bin_bound + 1e-9
+
+
+def test_batch_plan_rejects_bad_schedules():
+    wl = W.config5(ndomains=4)
+    p = lbm.make_batch_params("D3Q19", "f32", wl.domains)
+    for s in [lbm.make_batch_schedule("stepwise"), lbm.make_batch_schedule("persistent", 1, 2, 300, 0),
+              lbm.make_batch_schedule("persistent", 1, 0, 256, 0), lbm.make_batch_schedule("persistent", 2, 1, 256, 0),
+              lbm.make_batch_schedule("persistent", 1, 1, 256, -1)]:
+        with pytest.raises(lbm.LBMError) as e:
+            lbm.lbm_batch_plan(p, s, 256)
+        assert e.value.code == lbm.LBM_ERR_ARG
