@@ -26,7 +26,7 @@ namespace {
 
 constexpr int64_t kMaxWorkGroups = 16384;      // persistent grid bound (work-group lists in scratch)
 constexpr int64_t kMaxDomains = 1 << 24;
-constexpr int64_t kStrideCells = 128;          // plane stride granularity: 256 B at 2-byte storage
+constexpr int64_t kDomainAlign = 128;          // elements per domain block granularity: 256 B at 2-byte storage
 constexpr uint32_t kDefaultSpinLimit = 1u << 20;
 
 // Everything that follows from the parameters alone.
@@ -84,11 +84,11 @@ int plan_of(const lbm_batch_params *p, Plan &pl)
         BatchDomain &b = pl.dom[(size_t)i];
         std::memset(&b, 0, sizeof b);
         const int64_t n = (int64_t)pr.n;
-        const int64_t stride = (n + kStrideCells - 1) / kStrideCells * kStrideCells;
-        b.g.nx = (int32_t)dm.nx;
-        b.g.ny = (int32_t)dm.ny;
-        b.g.nz = (int32_t)dm.nz;
-        b.g.n = (uint32_t)stride;
+        // a domain is addressed with one 32-bit byte offset (tiles may span its z-planes)
+        if ((double)pr.q * (double)n * pr.bytes >= 4294967296.0)
+            return fail(LBM_ERR_SIZE, "domain %lld holds 4 GiB or more of populations", (long long)i);
+        const int64_t elems = (pr.q * n + kDomainAlign - 1) / kDomainAlign * kDomainAlign;
+        b.g = grid_of(dm.nx, dm.ny, dm.nz, pr.q, pr.bytes);
         b.cells = pr.n;
         b.mx = dm.nx == 1 ? 0xffffffffu : (uint32_t)(4294967296.0 / (double)dm.nx);
         b.my = dm.ny == 1 ? 0xffffffffu : (uint32_t)(4294967296.0 / (double)dm.ny);
@@ -101,7 +101,7 @@ int plan_of(const lbm_batch_params *p, Plan &pl)
         b.base = (uint64_t)base;
         b.cell0 = (uint64_t)cell0;
         for (int64_t t = 0; t < nt; ++t) pl.tiles.push_back(TileRec{(uint32_t)i, (uint32_t)(t * kTileCells)});
-        base += (int64_t)pr.q * stride;
+        base += elems;
         cell0 += n;
         tile0 += nt;
         if (tile0 >= 2147483647LL) return fail(LBM_ERR_SIZE, "batch exceeds 2^31 tiles");
@@ -262,7 +262,7 @@ int plan_persistent(const Plan &pl, const lbm_batch_schedule &s, int cu_count, P
     std::vector<std::vector<size_t>> groups(1);
     int64_t used = 0;
     for (size_t d = 0; d < pl.dom.size(); ++d) {
-        const int64_t bytes = 2LL * pl.q * (int64_t)pl.dom[d].g.n * pl.bytes;
+        const int64_t bytes = 2LL * pl.q * (int64_t)pl.dom[d].cells * pl.bytes;
         if (s.group_bytes > 0 && !groups.back().empty() && used + bytes > s.group_bytes) {
             groups.emplace_back();
             used = 0;

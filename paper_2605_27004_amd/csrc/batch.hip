@@ -28,49 +28,36 @@ namespace {
 
 using namespace cell;
 
-// floor(n / d) and n mod d from m = floor(2^32 / d) (0xffffffff for d = 1): the estimate
-// umulhi(n, m) is exact or one too small for every 32-bit n, so one correction suffices
-// (division by invariant integers using multiplication, Granlund and Montgomery).
-__device__ inline uint32_t div_by(uint32_t n, uint32_t m, uint32_t d, uint32_t &rem)
-{
-    uint32_t q = __umulhi(n, m);
-    uint32_t r = n - q * d;
-    if (r >= d) {
-        r -= d;
-        ++q;
-    }
-    rem = r;
-    return q;
-}
-
-__device__ inline Cell batch_cell(const BatchDomain &dm, uint32_t n)
+// Cell n (x fastest) of a domain; a tile may span z-planes, so batched domains use one 32-bit
+// index over the domain's whole block of the population arrays.
+__device__ inline FlatCell batch_cell(const BatchDomain &dm, uint32_t n)
 {
     uint32_t x, y;
     const uint32_t r = div_by(n, dm.mx, (uint32_t)dm.g.nx, x);
     const uint32_t z = div_by(r, dm.my, (uint32_t)dm.g.ny, y);
-    return cell_of(dm.g, (int32_t)x, (int32_t)y, (int32_t)z);
+    return flat_cell_of(dm.g, x, y, z);
 }
 
 // One periodic cell update: q pulls, the collision, q streaming stores.
 template <int LAT, typename S, int ORDER>
-__device__ inline void step_cell(const S *__restrict__ src, S *__restrict__ dst, uint32_t stride, const Cell &c,
+__device__ inline void step_cell(const S *__restrict__ src, S *__restrict__ dst, const Grid &g, const FlatCell &c,
                                  const StepConsts<typename Conv<S>::C> &k)
 {
     using C = typename Conv<S>::C;
     constexpr int NP = Lattice<LAT>::NP;
     C gp[NP + 1], gm[NP + 1];
-    gp[0] = Conv<S>::ld(ld_at(plane(src, 0, stride), c.own));
+    gp[0] = Conv<S>::ld(ld_pop(src, g, 0, own_ref(c)));
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-        gp[p + 1] = Conv<S>::ld(ld_at(plane(src, 2 * p + 1, stride), src_plus<LAT>(c, p)));
-        gm[p + 1] = Conv<S>::ld(ld_at(plane(src, 2 * p + 2, stride), src_minus<LAT>(c, p)));
+        gp[p + 1] = Conv<S>::ld(ld_pop(src, g, 2 * p + 1, src_plus<LAT>(c, p)));
+        gm[p + 1] = Conv<S>::ld(ld_pop(src, g, 2 * p + 2, src_minus<LAT>(c, p)));
     }
     collide_cell<LAT, ORDER, false, C, kClose<S>>(k, gp, gm);
-    st_stream(plane(dst, 0, stride), c.own, Conv<S>::st(gp[0]));
+    st_pop_stream(dst, g, 0, own_ref(c), Conv<S>::st(gp[0]));
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-        st_stream(plane(dst, 2 * p + 1, stride), c.own, Conv<S>::st(gp[p + 1]));
-        st_stream(plane(dst, 2 * p + 2, stride), c.own, Conv<S>::st(gm[p + 1]));
+        st_pop_stream(dst, g, 2 * p + 1, own_ref(c), Conv<S>::st(gp[p + 1]));
+        st_pop_stream(dst, g, 2 * p + 2, own_ref(c), Conv<S>::st(gm[p + 1]));
     }
 }
 
@@ -86,7 +73,7 @@ __global__ __launch_bounds__(kTileCells) void k_batch_step(const S *__restrict__
     const uint32_t n = t.first + threadIdx.x;
     if (n >= dm.cells) return;
     const StepConsts<typename Conv<S>::C> k = kc[t.dom];
-    step_cell<LAT, S, ORDER>(src + dm.base, dst + dm.base, dm.g.n, batch_cell(dm, n), k);
+    step_cell<LAT, S, ORDER>(src + dm.base, dst + dm.base, dm.g, batch_cell(dm, n), k);
 }
 
 // ---- the persistent launch ------------------------------------------------------------------
@@ -167,7 +154,7 @@ __global__ __launch_bounds__(kTileCells) void k_batch_persist(
                 const BatchDomain dm = doms[dom];
                 const StepConsts<C> k = kc[dom];
                 for (uint32_t off = threadIdx.x; off < count; off += kTileCells)
-                    step_cell<LAT, S, ORDER>(src + dm.base, dst + dm.base, dm.g.n, batch_cell(dm, first + off), k);
+                    step_cell<LAT, S, ORDER>(src + dm.base, dst + dm.base, dm.g, batch_cell(dm, first + off), k);
                 arrive(ctr + dom);
             }
         }
@@ -195,7 +182,7 @@ __global__ __launch_bounds__(kTileCells) void k_batch_init(const TileRec *__rest
     const uint32_t n = t.first + threadIdx.x;
     if (n >= dm.cells) return;
     const StepConsts<double> &k = kc[t.dom];
-    const Cell c = batch_cell(dm, n);
+    const FlatCell c = batch_cell(dm, n);
     const uint64_t at = dm.cell0 + n;
     const double rho = rho_in[at];
     const double sx = s_in[at], sy = s_in[ncells + at];
@@ -203,11 +190,11 @@ __global__ __launch_bounds__(kTileCells) void k_batch_init(const TileRec *__rest
     double eqp[NP + 1], eqm[NP + 1];
     equilibrium_pairs<LAT, ORDER, double>(k, rho - k.rho0, rho, sx, sy, sz, eqp, eqm);
     S *out = dst + dm.base;
-    st_at(plane(out, 0, dm.g.n), c.own, Conv<S>::st((C)eqp[0]));
+    st_pop(out, dm.g, 0, own_ref(c), Conv<S>::st((C)eqp[0]));
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-        st_at(plane(out, 2 * p + 1, dm.g.n), src_plus<LAT>(c, p), Conv<S>::st((C)eqp[p + 1]));
-        st_at(plane(out, 2 * p + 2, dm.g.n), src_minus<LAT>(c, p), Conv<S>::st((C)eqm[p + 1]));
+        st_pop(out, dm.g, 2 * p + 1, src_plus<LAT>(c, p), Conv<S>::st((C)eqp[p + 1]));
+        st_pop(out, dm.g, 2 * p + 2, src_minus<LAT>(c, p), Conv<S>::st((C)eqm[p + 1]));
     }
 }
 
@@ -229,14 +216,14 @@ __global__ __launch_bounds__(kTileCells) void k_batch_moments(const TileRec *__r
     const uint32_t n = t.first + threadIdx.x;
     double acc[kBatchPartials] = {0.0, 0.0, 0.0, 0.0};
     if (n < dm.cells) {
-        const Cell c = batch_cell(dm, n);
+        const FlatCell c = batch_cell(dm, n);
         const S *in = src + dm.base;
         double gp[NP + 1], gm[NP + 1];
-        gp[0] = (double)Conv<S>::ld(ld_at(plane(in, 0, dm.g.n), c.own));
+        gp[0] = (double)Conv<S>::ld(ld_pop(in, dm.g, 0, own_ref(c)));
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
-            gp[p + 1] = (double)Conv<S>::ld(ld_at(plane(in, 2 * p + 1, dm.g.n), src_plus<LAT>(c, p)));
-            gm[p + 1] = (double)Conv<S>::ld(ld_at(plane(in, 2 * p + 2, dm.g.n), src_minus<LAT>(c, p)));
+            gp[p + 1] = (double)Conv<S>::ld(ld_pop(in, dm.g, 2 * p + 1, src_plus<LAT>(c, p)));
+            gm[p + 1] = (double)Conv<S>::ld(ld_pop(in, dm.g, 2 * p + 2, src_minus<LAT>(c, p)));
         }
         double drho, jx, jy, jz;
         moments_of<LAT>(gp, gm, drho, jx, jy, jz);
@@ -296,16 +283,16 @@ __global__ __launch_bounds__(kTileCells) void k_batch_export(const TileRec *__re
     const uint32_t n = t.first + threadIdx.x;
     if (n >= dm.cells) return;
     const StepConsts<double> &k = kc[t.dom];
-    const Cell c = batch_cell(dm, n);
+    const FlatCell c = batch_cell(dm, n);
     const S *in = src + dm.base;
     double *o = out + (uint64_t)L::Q * dm.cell0;
-    o[n] = (double)Conv<S>::ld(ld_at(plane(in, 0, dm.g.n), c.own)) + k.sigma[0];
+    o[n] = (double)Conv<S>::ld(ld_pop(in, dm.g, 0, own_ref(c))) + k.sigma[0];
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
         o[(uint64_t)(2 * p + 1) * dm.cells + n] =
-            (double)Conv<S>::ld(ld_at(plane(in, 2 * p + 1, dm.g.n), src_plus<LAT>(c, p))) + k.sigma[p + 1];
+            (double)Conv<S>::ld(ld_pop(in, dm.g, 2 * p + 1, src_plus<LAT>(c, p))) + k.sigma[p + 1];
         o[(uint64_t)(2 * p + 2) * dm.cells + n] =
-            (double)Conv<S>::ld(ld_at(plane(in, 2 * p + 2, dm.g.n), src_minus<LAT>(c, p))) + k.sigma[p + 1];
+            (double)Conv<S>::ld(ld_pop(in, dm.g, 2 * p + 2, src_minus<LAT>(c, p))) + k.sigma[p + 1];
     }
 }
 

@@ -2,10 +2,11 @@
 // batched update: many independent periodic domains of uneven sizes, each with its own
 // tensor and relaxation time, advanced together.
 //
-// Storage. Domain d owns a block of both population arrays starting at element `base`:
-// q planes of `stride` cells each (stride = cells rounded up to 128, so every plane starts on
-// a 256-byte boundary in every storage type), cells in x-fastest order. Host arrays of rho and s
-// concatenate the domains' cells without padding, from cell offset `cell0`.
+// Storage. Domain d owns a stretch of both population arrays starting at element `base`
+// (q cells elements rounded up to 128, so every domain starts on a 256-byte boundary in every
+// storage type), holding the domain's populations in the blocked layout of its Grid. Host
+// arrays of rho and s concatenate the domains' cells (x fastest) without padding, from cell
+// offset `cell0`.
 //
 // Work units. A tile is 256 consecutive cells of one domain (the last tile of a domain may be
 // short). The step-per-launch mode runs one work-group per tile. The persistent mode hands
@@ -22,7 +23,7 @@ namespace lbm {
 constexpr int kTileCells = 256;
 
 struct BatchDomain {
-    Grid g;            // nx, ny, nz and n = the plane stride in cells
+    Grid g;            // extents and population layout of the domain
     uint32_t cells;    // nx * ny * nz
     uint32_t mx, my;   // floor(2^32 / nx), floor(2^32 / ny) (0xffffffff for 1): cell index -> x, y, z
     uint32_t tile0;    // first tile of this domain in the natural (domain-major) tile order

@@ -133,6 +133,29 @@ double det_from_cholesky(int d, const double *l)
 }
 
 
+Grid grid_of(int64_t nx, int64_t ny, int64_t nz, int q, int bytes)
+{
+    Grid g{};
+    g.nx = (int32_t)nx;
+    g.ny = (int32_t)ny;
+    g.nz = (int32_t)nz;
+    g.n = (uint32_t)(nx * ny * nz);
+    int64_t rows = 1;
+    for (int64_t r = ny; r >= 1; --r)
+        if (ny % r == 0 && r * nx * bytes <= kBlockBytes) {
+            rows = r;
+            break;
+        }
+    g.rows = (uint32_t)rows;
+    g.mr = rows == 1 ? 0xffffffffu : (uint32_t)(4294967296.0 / (double)rows);
+    // floor(2^32 / rows) exactly (the double quotient can round up at the last bit)
+    if (rows > 1 && (uint64_t)g.mr * (uint64_t)rows > 4294967296ull) --g.mr;
+    g.bc = (uint32_t)(rows * nx);
+    g.bq = (uint32_t)(q * rows * nx);
+    g.zs = (uint32_t)(q * nx * ny);
+    return g;
+}
+
 int prepare(const lbm_params *p, Prepared &out)
 {
     if (!p) return fail(LBM_ERR_ARG, "params is NULL");
@@ -161,6 +184,10 @@ int prepare(const lbm_params *p, Prepared &out)
     // 32-bit cell indices and 32-bit byte offsets inside each population plane
     if (nd >= 2147483648.0 || nd * out.bytes >= 4294967296.0)
         return fail(LBM_ERR_SIZE, "grid of %.0f cells exceeds the 2^31-cell / 4 GiB-per-plane limit", nd);
+    // the population layout indexes one z-plane with 32-bit byte offsets
+    if ((double)q * (double)p->nx * (double)p->ny * out.bytes >= 4294967296.0)
+        return fail(LBM_ERR_SIZE, "one z-plane of %lld x %lld cells holds 4 GiB or more of populations",
+                    (long long)p->nx, (long long)p->ny);
     out.n = (uint32_t)(p->nx * p->ny * p->nz);
     if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LBM_ERR_TAU, "tau must be > 1/2 (got %g)", p->tau);
     if (!(p->rho0 > 0.0) || !std::isfinite(p->rho0)) return fail(LBM_ERR_ARG, "rho0 must be > 0 (got %g)", p->rho0);
@@ -324,7 +351,7 @@ int64_t lbm_scratch_bytes(const lbm_params *p)
 {
     Prepared pr;
     if (prepare(p, pr)) return -1;
-    Grid g{(int32_t)p->nx, (int32_t)p->ny, (int32_t)p->nz, pr.n};
+    const Grid g = grid_of(p->nx, p->ny, p->nz, pr.q, pr.bytes);
     // kPartials sums per reduction block, then kPartials totals, rounded up to 256 bytes
     const int64_t bytes = 8 * (kPartials * (int64_t)moments_blocks(g) + kPartials);
     return links_bytes(*p, pr.n) + (bytes + 255) / 256 * 256;
@@ -350,7 +377,7 @@ int lbm_init(lbm_ctx **out, const lbm_params *p, void *pop_a, void *pop_b, void 
     if (!c) return fail(LBM_ERR_ARG, "out of host memory");
     c->p = *p;
     c->pr = pr;
-    c->grid = Grid{(int32_t)p->nx, (int32_t)p->ny, (int32_t)p->nz, pr.n};
+    c->grid = grid_of(p->nx, p->ny, p->nz, pr.q, pr.bytes);
     c->k64 = consts_for<double>(*p, pr);
     c->k32 = consts_for<float>(*p, pr);
     c->pop[0] = pop_a;

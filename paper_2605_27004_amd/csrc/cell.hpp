@@ -53,55 +53,153 @@ template <> struct Conv<__bf16> {
 // The moment closure runs for FP32 storage only (see collide_cell).
 template <typename S> constexpr bool kClose = std::is_same<S, float>::value;
 
-// ---- neighbourhood ---------------------------------------------------------------------
+// ---- neighbourhood and population addressing ----------------------------------------
+//
+// Population arrays use the blocked layout of Grid. Because `rows` divides ny, the storage
+// offset from a cell to a neighbour is a sum of one term per axis -- the x-term depends on x
+// only, the y-term on y only, the z-term on z only -- so a neighbour costs the same few adds
+// as in a plain plane-per-direction layout, with the periodic wrap folded into the terms.
 
-// Offsets (in cells) from a cell to its periodic neighbours at coordinate -1 and +1 along
-// one axis.
+// floor(n / d) and n mod d from m = floor(2^32 / d) (0xffffffff for d = 1): the estimate
+// umulhi(n, m) is exact or one too small for every 32-bit n, so one correction suffices
+// (division by invariant integers using multiplication, Granlund and Montgomery).
+__device__ inline uint32_t div_by(uint32_t n, uint32_t m, uint32_t d, uint32_t &rem)
+{
+    uint32_t q = __umulhi(n, m);
+    uint32_t r = n - q * d;
+    if (r >= d) {
+        r -= d;
+        ++q;
+    }
+    rem = r;
+    return q;
+}
+
+// Offsets (in elements, modulo 2^32) from a cell to its periodic neighbours at coordinate -1
+// and +1 along one axis.
 struct AxisOff {
-    int32_t m1, p1;
+    uint32_t m1, p1;
 };
 
-__device__ inline AxisOff axis_off(int32_t v, int32_t n, int32_t stride)
+__device__ inline AxisOff axis_off(uint32_t v, uint32_t n, uint32_t stride)
 {
     AxisOff o;
-    o.m1 = (v == 0) ? (n - 1) * stride : -stride;
-    o.p1 = (v == n - 1) ? -(n - 1) * stride : stride;
+    o.m1 = (v == 0) ? (n - 1u) * stride : 0u - stride;
+    o.p1 = (v == n - 1u) ? 0u - (n - 1u) * stride : stride;
     return o;
 }
 
 // Offset to the cell x - c for one velocity component c in {-1, 0, 1} (a constant after
 // unrolling).
-__device__ inline int32_t back(const AxisOff &o, int c) { return c > 0 ? o.m1 : (c < 0 ? o.p1 : 0); }
+__device__ inline uint32_t back(const AxisOff &o, int c) { return c > 0 ? o.m1 : (c < 0 ? o.p1 : 0u); }
 
+// Storage offset of row y within its z-plane, and the offsets to rows y - 1 and y + 1.
+__device__ inline uint32_t row_off(const Grid &g, uint32_t y, AxisOff &oy)
+{
+    uint32_t yr;
+    const uint32_t yb = div_by(y, g.mr, g.rows, yr);
+    const uint32_t last = g.zs - g.bq + (g.rows - 1u) * (uint32_t)g.nx;  // row ny - 1
+    const uint32_t cross = g.bq - (g.rows - 1u) * (uint32_t)g.nx;        // row to the next block's first
+    oy.m1 = (y == 0u) ? last : (yr == 0u ? 0u - cross : 0u - (uint32_t)g.nx);
+    oy.p1 = (y == (uint32_t)g.ny - 1u) ? 0u - last : (yr == g.rows - 1u ? cross : (uint32_t)g.nx);
+    return yb * g.bq + yr * (uint32_t)g.nx;
+}
+
+// Location of one population: an element offset that is the same for the whole work-group
+// (the z-plane) plus a per-lane 32-bit index.
+struct Ref {
+    uint64_t zo;
+    uint32_t idx;
+};
+
+// A cell of a single grid. Every kernel over a single grid runs work-groups inside one
+// z-plane, so the z-plane offsets are work-group uniform (scalar registers) and the per-lane
+// index stays within one z-plane, whatever the size of the grid.
 struct Cell {
-    uint32_t own;
-    AxisOff ox, oy, oz;
+    uint32_t own;         // canonical index x + nx (y + ny z)
+    uint32_t at;          // storage index within the z-plane
+    AxisOff ox, oy;
+    uint64_t z0, zm, zp;  // element offsets of the z-planes z, z - 1 and z + 1 (periodic)
 };
 
 __device__ inline Cell cell_of(const Grid &g, int32_t x, int32_t y, int32_t z)
 {
     Cell c;
     c.own = (uint32_t)((z * g.ny + y) * g.nx + x);
-    c.ox = axis_off(x, g.nx, 1);
-    c.oy = axis_off(y, g.ny, g.nx);
-    c.oz = axis_off(z, g.nz, g.nx * g.ny);
+    c.ox = axis_off((uint32_t)x, (uint32_t)g.nx, 1u);
+    c.at = row_off(g, (uint32_t)y, c.oy) + (uint32_t)x;
+    c.z0 = (uint64_t)z * g.zs;
+    c.zm = (uint64_t)(z == 0 ? g.nz - 1 : z - 1) * g.zs;
+    c.zp = (uint64_t)(z == g.nz - 1 ? 0 : z + 1) * g.zs;
     return c;
 }
 
-template <int LAT> __device__ inline uint32_t src_plus(const Cell &c, int p)
+// A cell addressed with one 32-bit index over the whole grid: a batched domain (whose
+// populations stay below 4 GiB), or canonical order for per-cell arrays (canon_cell_of).
+struct FlatCell {
+    uint32_t own;  // canonical index
+    uint32_t at;   // storage (or canonical) index
+    AxisOff ox, oy, oz;
+};
+
+__device__ inline FlatCell flat_cell_of(const Grid &g, uint32_t x, uint32_t y, uint32_t z)
 {
-    const PairRow v = Lattice<LAT>::pair(p);
-    return c.own + (uint32_t)(back(c.ox, v.cx) + back(c.oy, v.cy) + back(c.oz, v.cz));
+    FlatCell c;
+    c.own = (z * (uint32_t)g.ny + y) * (uint32_t)g.nx + x;
+    c.ox = axis_off(x, (uint32_t)g.nx, 1u);
+    c.at = z * g.zs + row_off(g, y, c.oy) + x;
+    c.oz = axis_off(z, (uint32_t)g.nz, g.zs);
+    return c;
 }
 
-template <int LAT> __device__ inline uint32_t src_minus(const Cell &c, int p)
+__device__ inline FlatCell canon_cell_of(const Grid &g, uint32_t x, uint32_t y, uint32_t z)
 {
-    const PairRow v = Lattice<LAT>::pair(p);
-    return c.own + (uint32_t)(back(c.ox, -v.cx) + back(c.oy, -v.cy) + back(c.oz, -v.cz));
+    FlatCell c;
+    c.own = (z * (uint32_t)g.ny + y) * (uint32_t)g.nx + x;
+    c.at = c.own;
+    c.ox = axis_off(x, (uint32_t)g.nx, 1u);
+    c.oy = axis_off(y, (uint32_t)g.ny, (uint32_t)g.nx);
+    c.oz = axis_off(z, (uint32_t)g.nz, (uint32_t)g.nx * (uint32_t)g.ny);
+    return c;
 }
 
-// Element `idx` of population plane i; plane bases are wave-uniform and the per-lane offset
-// stays a 32-bit byte offset (planes are < 4 GiB).
+__device__ inline Ref own_ref(const Cell &c) { return Ref{c.z0, c.at}; }
+__device__ inline Ref own_ref(const FlatCell &c) { return Ref{0u, c.at}; }
+
+// The cell x - c (sign +1) or x + c (sign -1) for velocity c = (cx, cy, cz).
+__device__ inline Ref nbr(const Cell &c, int cx, int cy, int cz)
+{
+    return Ref{cz > 0 ? c.zm : (cz < 0 ? c.zp : c.z0), c.at + back(c.ox, cx) + back(c.oy, cy)};
+}
+__device__ inline Ref nbr(const FlatCell &c, int cx, int cy, int cz)
+{
+    return Ref{0u, c.at + back(c.ox, cx) + back(c.oy, cy) + back(c.oz, cz)};
+}
+
+// x - c and x + c for the velocity c of pair p.
+template <int LAT, typename CellT> __device__ inline Ref src_plus(const CellT &c, int p)
+{
+    const PairRow v = Lattice<LAT>::pair(p);
+    return nbr(c, v.cx, v.cy, v.cz);
+}
+template <int LAT, typename CellT> __device__ inline Ref src_minus(const CellT &c, int p)
+{
+    const PairRow v = Lattice<LAT>::pair(p);
+    return nbr(c, -v.cx, -v.cy, -v.cz);
+}
+
+// Element of direction i at r in a population array (plane bases and the z-plane offset are
+// work-group uniform; the per-lane offset stays a 32-bit byte offset).
+template <typename S> __device__ inline const S *pop_base(const S *base, const Grid &g, int i, const Ref &r)
+{
+    return base + r.zo + (uint64_t)i * g.bc;
+}
+template <typename S> __device__ inline S *pop_base(S *base, const Grid &g, int i, const Ref &r)
+{
+    return base + r.zo + (uint64_t)i * g.bc;
+}
+
+// Element `idx` of canonical plane i of a [q][n] array.
 template <typename S> __device__ inline const S *plane(const S *base, int i, uint32_t n)
 {
     return base + (size_t)i * n;
@@ -122,6 +220,19 @@ template <typename S> __device__ inline void st_at(S *p, uint32_t idx, S v)
 template <typename S> __device__ inline void st_stream(S *p, uint32_t idx, S v)
 {
     __builtin_nontemporal_store(v, reinterpret_cast<S *>(reinterpret_cast<char *>(p) + (uint32_t)(idx * (uint32_t)sizeof(S))));
+}
+
+template <typename S> __device__ inline S ld_pop(const S *base, const Grid &g, int i, const Ref &r)
+{
+    return ld_at(pop_base(base, g, i, r), r.idx);
+}
+template <typename S> __device__ inline void st_pop(S *base, const Grid &g, int i, const Ref &r, S v)
+{
+    st_at(pop_base(base, g, i, r), r.idx, v);
+}
+template <typename S> __device__ inline void st_pop_stream(S *base, const Grid &g, int i, const Ref &r, S v)
+{
+    st_stream(pop_base(base, g, i, r), r.idx, v);
 }
 
 // ---- the collision -----------------------------------------------------------------------
@@ -302,22 +413,64 @@ __device__ inline void collide_cell(const StepConsts<C> &k, C *gp, C *gm)
 // Where the canonical pre-collision population i of a cell lives in the state: normally the
 // post-collision value of the upstream cell x - c_i (pull streaming); when that cell is solid,
 // the cell's own post-collision value of the opposite direction (halfway bounce-back). The
-// link word has bit i set in the second case.
+// link word has bit i set in the second case. A slot keeps both candidates. When they lie in
+// the same z-plane (c_z = 0, or a flat cell), both are offsets from one work-group-uniform
+// plane base and resolving the slot selects a 32-bit index; otherwise it selects between two
+// uniform plane bases.
 struct Slot {
-    int plane;
-    uint32_t idx;
+    bool bounce;
+    bool same_z;  // a constant after unrolling
+    int own_plane, src_plane;
+    Ref own, src;
 };
 
-template <int LAT> __device__ inline Slot slot_plus(const Cell &c, int p, uint32_t links)
+__device__ inline bool same_z(const Cell &, int cz) { return cz == 0; }
+__device__ inline bool same_z(const FlatCell &, int) { return true; }
+
+template <int LAT, typename CellT> __device__ inline Slot slot_plus(const CellT &c, int p, uint32_t links)
 {
-    if (links >> (2 * p + 1) & 1u) return Slot{2 * p + 2, c.own};
-    return Slot{2 * p + 1, src_plus<LAT>(c, p)};
+    const bool bounce = (links >> (2 * p + 1) & 1u) != 0u;
+    return Slot{bounce, same_z(c, Lattice<LAT>::pair(p).cz), 2 * p + 2, 2 * p + 1, own_ref(c), src_plus<LAT>(c, p)};
 }
 
-template <int LAT> __device__ inline Slot slot_minus(const Cell &c, int p, uint32_t links)
+template <int LAT, typename CellT> __device__ inline Slot slot_minus(const CellT &c, int p, uint32_t links)
 {
-    if (links >> (2 * p + 2) & 1u) return Slot{2 * p + 1, c.own};
-    return Slot{2 * p + 2, src_minus<LAT>(c, p)};
+    const bool bounce = (links >> (2 * p + 2) & 1u) != 0u;
+    return Slot{bounce, same_z(c, Lattice<LAT>::pair(p).cz), 2 * p + 1, 2 * p + 2, own_ref(c), src_minus<LAT>(c, p)};
+}
+
+// A slot that is always the given plane at r (no bounce-back alternative).
+__device__ inline Slot fixed_slot(int plane, const Ref &r) { return Slot{false, true, plane, plane, r, r}; }
+
+// Plane base and per-lane index of a slot.
+template <typename S> __device__ inline void slot_at(S *base, const Grid &g, const Slot &s, S *&p, uint32_t &idx)
+{
+    if (s.same_z) {
+        const int lo = s.own_plane < s.src_plane ? s.own_plane : s.src_plane;
+        p = pop_base(base, g, lo, s.src);
+        const uint32_t io = s.own.idx + (uint32_t)(s.own_plane - lo) * g.bc;
+        const uint32_t is = s.src.idx + (uint32_t)(s.src_plane - lo) * g.bc;
+        idx = s.bounce ? io : is;
+    } else {
+        S *a = pop_base(base, g, s.own_plane, s.own), *b = pop_base(base, g, s.src_plane, s.src);
+        p = s.bounce ? a : b;
+        idx = s.bounce ? s.own.idx : s.src.idx;
+    }
+}
+
+template <typename S> __device__ inline S ld_slot(const S *base, const Grid &g, const Slot &s)
+{
+    const S *p;
+    uint32_t idx;
+    slot_at(base, g, s, p, idx);
+    return ld_at(p, idx);
+}
+template <typename S> __device__ inline void st_slot(S *base, const Grid &g, const Slot &s, S v)
+{
+    S *p;
+    uint32_t idx;
+    slot_at(base, g, s, p, idx);
+    st_at(p, idx, v);
 }
 
 }  // namespace cell

@@ -35,9 +35,22 @@ template <typename C> struct StepConsts {
     int32_t forced;         // F != 0
 };
 
+// Grid extents and the storage layout of its population arrays (both state buffers and the
+// adjoint's lam buffers; counted in elements, so one layout serves every element type).
+// Populations are stored z-plane by z-plane. A z-plane is cut into ny / rows blocks of `rows`
+// consecutive y-rows (rows divides ny), and a block holds its q direction planes one after
+// another, bc = rows nx cells each. Direction i of cell (x, y, z) is element
+//     z zs + (y / rows) bq + i bc + (y mod rows) nx + x,      bq = q bc,  zs = q nx ny.
+// Canonical arrays (masks, link words, per-cell fields, exported populations) keep the plain
+// order x + nx (y + ny z).
 struct Grid {
     int32_t nx, ny, nz;
-    uint32_t n;  // cells = nx * ny * nz (< 2^31)
+    uint32_t n;     // cells = nx * ny * nz (< 2^31)
+    uint32_t rows;  // y-rows per block
+    uint32_t mr;    // floor(2^32 / rows) (0xffffffff for rows = 1): y -> (y / rows, y mod rows)
+    uint32_t bc;    // rows nx: cells per block and direction
+    uint32_t bq;    // q bc: elements per block
+    uint32_t zs;    // q nx ny: elements per z-plane (the bytes of one z-plane stay below 4 GiB)
 };
 
 // ---- launchers (kernels.hip) -----------------------------------------------------------

@@ -47,6 +47,16 @@ int prepare(const lbm_params *p, Prepared &out);
 // Kernel constants of one parameter set in arithmetic precision C.
 template <typename C> StepConsts<C> consts_for(const lbm_params &p, const Prepared &pr);
 
+// Target bytes of one direction plane of one block in the population layout (Grid): rows per
+// block is the largest divisor of ny with rows * nx * bytes <= kBlockBytes, at least 1.
+// Blocks of about this size keep a work-group's 2q population streams within one compact
+// stretch of memory; measured on the D3Q19 step, 8 KiB was best for FP32.
+constexpr int64_t kBlockBytes = 8192;
+
+// Extents and population layout of an nx x ny x nz grid of q directions in `bytes`-byte
+// storage (the caller has validated the sizes).
+Grid grid_of(int64_t nx, int64_t ny, int64_t nz, int q, int bytes);
+
 int64_t align256(int64_t b);
 bool aligned256(const void *ptr);
 

@@ -1,9 +1,10 @@
 // kernels.hip -- gfx950 kernels of the anisotropic-equilibrium BGK lattice Boltzmann update.
 //
-// State layout. Populations live in two structure-of-arrays buffers [q][nz][ny][nx] (x
-// fastest) of deviations g_i = f_i - sigma_i in the storage type S. After k steps the
+// State layout. Populations live in two buffers of deviations g_i = f_i - sigma_i in the
+// storage type S, in the blocked layout of Grid (each z-plane a run of blocks of a few
+// y-rows, every block holding its q direction planes back to back). After k steps the
 // current buffer holds the POST-collision values of step k-1 at their own cell, so the
-// canonical pre-collision state is the gather f_i(k, x) = sigma_i + state[i][x - c_i]
+// canonical pre-collision state is the gather f_i(k, x) = sigma_i + state_i(x - c_i)
 // (periodic wrap). One step is therefore a single pass over HBM: gather q values along
 // -c_i (pull streaming), form rho and s, build the equilibrium, relax, and store q values
 // at the cell itself into the other buffer (eq:LBE_BGK). The initial state is written to
@@ -92,21 +93,21 @@ __global__ __launch_bounds__(256) void k_step(const S *__restrict__ src, S *__re
 #pragma unroll
             for (int p = 0; p <= NP; ++p) gp[p] = gm[p] = C(0);
         } else {
-            gp[0] = Conv<S>::ld(ld_at(plane(src, 0, g.n), c.own));
+            gp[0] = Conv<S>::ld(ld_pop(src, g, 0, own_ref(c)));
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
                 const Slot sp = slot_plus<LAT>(c, p, lk), sm = slot_minus<LAT>(c, p, lk);
-                gp[p + 1] = Conv<S>::ld(ld_at(plane(src, sp.plane, g.n), sp.idx));
-                gm[p + 1] = Conv<S>::ld(ld_at(plane(src, sm.plane, g.n), sm.idx));
+                gp[p + 1] = Conv<S>::ld(ld_slot(src, g, sp));
+                gm[p + 1] = Conv<S>::ld(ld_slot(src, g, sm));
             }
             collide_cell<LAT, ORDER, true, C, kClose<S>>(k, gp, gm);
         }
     } else {
-        gp[0] = Conv<S>::ld(ld_at(plane(src, 0, g.n), c.own));
+        gp[0] = Conv<S>::ld(ld_pop(src, g, 0, own_ref(c)));
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
-            gp[p + 1] = Conv<S>::ld(ld_at(plane(src, 2 * p + 1, g.n), src_plus<LAT>(c, p)));
-            gm[p + 1] = Conv<S>::ld(ld_at(plane(src, 2 * p + 2, g.n), src_minus<LAT>(c, p)));
+            gp[p + 1] = Conv<S>::ld(ld_pop(src, g, 2 * p + 1, src_plus<LAT>(c, p)));
+            gm[p + 1] = Conv<S>::ld(ld_pop(src, g, 2 * p + 2, src_minus<LAT>(c, p)));
         }
     }
 
@@ -129,11 +130,11 @@ __global__ __launch_bounds__(256) void k_step(const S *__restrict__ src, S *__re
             gm[p + 1] = fmad(mg, pp[p + 1] - gm[p + 1], gm[p + 1]);
         }
     }
-    st_stream(plane(dst, 0, g.n), c.own, Conv<S>::st(gp[0]));
+    st_pop_stream(dst, g, 0, own_ref(c), Conv<S>::st(gp[0]));
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-        st_stream(plane(dst, 2 * p + 1, g.n), c.own, Conv<S>::st(gp[p + 1]));
-        st_stream(plane(dst, 2 * p + 2, g.n), c.own, Conv<S>::st(gm[p + 1]));
+        st_pop_stream(dst, g, 2 * p + 1, own_ref(c), Conv<S>::st(gp[p + 1]));
+        st_pop_stream(dst, g, 2 * p + 2, own_ref(c), Conv<S>::st(gm[p + 1]));
     }
 }
 
@@ -147,12 +148,12 @@ __global__ __launch_bounds__(256) void k_links(const uint8_t *__restrict__ mask,
     const int32_t y = blockIdx.y * blockDim.y + threadIdx.y;
     const int32_t z = blockIdx.z;
     if (x >= g.nx || y >= g.ny) return;
-    const Cell c = cell_of(g, x, y, z);
+    const FlatCell c = canon_cell_of(g, (uint32_t)x, (uint32_t)y, (uint32_t)z);
     uint32_t w = mask[c.own] ? 1u : 0u;
 #pragma unroll
     for (int p = 0; p < L::NP; ++p) {
-        if (mask[src_plus<LAT>(c, p)]) w |= 1u << (2 * p + 1);
-        if (mask[src_minus<LAT>(c, p)]) w |= 1u << (2 * p + 2);
+        if (mask[src_plus<LAT>(c, p).idx]) w |= 1u << (2 * p + 1);
+        if (mask[src_minus<LAT>(c, p).idx]) w |= 1u << (2 * p + 2);
     }
     links[c.own] = w;
 }
@@ -174,7 +175,7 @@ __global__ __launch_bounds__(256) void k_init(const double *__restrict__ rho_in,
     const Cell c = cell_of(g, x, y, z);
     const uint32_t lk = links ? links[c.own] : 0u;
     if (lk & 1u) {  // solid: no state; its own slots are set to zero like every step does
-        for (int i = 0; i < L::Q; ++i) st_at(plane(dst, i, g.n), c.own, Conv<S>::st(C(0)));
+        for (int i = 0; i < L::Q; ++i) st_pop(dst, g, i, own_ref(c), Conv<S>::st(C(0)));
         return;
     }
     const double rho = rho_in[c.own];
@@ -183,12 +184,12 @@ __global__ __launch_bounds__(256) void k_init(const double *__restrict__ rho_in,
     const double sz = (L::D == 3) ? s_in[2 * (size_t)g.n + c.own] : 0.0;
     double eqp[NP + 1], eqm[NP + 1];
     equilibrium_pairs<LAT, ORDER, double>(k, rho - k.rho0, rho, sx, sy, sz, eqp, eqm);
-    st_at(plane(dst, 0, g.n), c.own, Conv<S>::st((C)eqp[0]));
+    st_pop(dst, g, 0, own_ref(c), Conv<S>::st((C)eqp[0]));
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
         const Slot sp = slot_plus<LAT>(c, p, lk), sm = slot_minus<LAT>(c, p, lk);
-        st_at(plane(dst, sp.plane, g.n), sp.idx, Conv<S>::st((C)eqp[p + 1]));
-        st_at(plane(dst, sm.plane, g.n), sm.idx, Conv<S>::st((C)eqm[p + 1]));
+        st_slot(dst, g, sp, Conv<S>::st((C)eqp[p + 1]));
+        st_slot(dst, g, sm, Conv<S>::st((C)eqm[p + 1]));
     }
 }
 
@@ -216,12 +217,12 @@ __global__ __launch_bounds__(kRedThreads) void k_moments(const S *__restrict__ s
         double rho = 0.0, ux = 0.0, uy = 0.0, uz = 0.0;
         if (!(lk & 1u)) {
             double gp[NP + 1], gm[NP + 1];
-            gp[0] = (double)Conv<S>::ld(ld_at(plane(src, 0, g.n), c.own));
+            gp[0] = (double)Conv<S>::ld(ld_pop(src, g, 0, own_ref(c)));
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
                 const Slot sp = slot_plus<LAT>(c, p, lk), sm = slot_minus<LAT>(c, p, lk);
-                gp[p + 1] = (double)Conv<S>::ld(ld_at(plane(src, sp.plane, g.n), sp.idx));
-                gm[p + 1] = (double)Conv<S>::ld(ld_at(plane(src, sm.plane, g.n), sm.idx));
+                gp[p + 1] = (double)Conv<S>::ld(ld_slot(src, g, sp));
+                gm[p + 1] = (double)Conv<S>::ld(ld_slot(src, g, sm));
             }
             double drho, jx, jy, jz;
             moments_of<LAT>(gp, gm, drho, jx, jy, jz);
@@ -292,15 +293,15 @@ __global__ __launch_bounds__(256) void k_permute(const void *__restrict__ in, vo
     auto move = [&](int i, Slot sl, double sigma) {
         if constexpr (MODE == 0) {
             st_at(plane((S *)out, i, g.n), c.own,
-                  solid ? Conv<S>::st(typename Conv<S>::C(0)) : ld_at(plane((const S *)in, sl.plane, g.n), sl.idx));
+                  solid ? Conv<S>::st(typename Conv<S>::C(0)) : ld_slot((const S *)in, g, sl));
         } else if constexpr (MODE == 1) {
-            if (!solid) st_at(plane((S *)out, sl.plane, g.n), sl.idx, ld_at(plane((const S *)in, i, g.n), c.own));
+            if (!solid) st_slot((S *)out, g, sl, ld_at(plane((const S *)in, i, g.n), c.own));
         } else {
-            const double v = solid ? 0.0 : (double)Conv<S>::ld(ld_at(plane((const S *)in, sl.plane, g.n), sl.idx)) + sigma;
+            const double v = solid ? 0.0 : (double)Conv<S>::ld(ld_slot((const S *)in, g, sl)) + sigma;
             st_at(plane((double *)out, i, g.n), c.own, v);
         }
     };
-    move(0, Slot{0, c.own}, k.sigma[0]);
+    move(0, fixed_slot(0, own_ref(c)), k.sigma[0]);
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
         move(2 * p + 1, slot_plus<LAT>(c, p, lk), k.sigma[p + 1]);
@@ -459,12 +460,12 @@ __global__ __launch_bounds__(256) void k_seed(const S *__restrict__ src, typenam
         const Cell c = cell_of(g, x, y, z);
         const uint32_t lk = links ? links[c.own] : 0u;
         C gp[NP + 1], gm[NP + 1];
-        gp[0] = Conv<S>::ld(ld_at(plane(src, 0, g.n), c.own));
+        gp[0] = Conv<S>::ld(ld_pop(src, g, 0, own_ref(c)));
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
             const Slot sp = slot_plus<LAT>(c, p, lk), sm = slot_minus<LAT>(c, p, lk);
-            gp[p + 1] = Conv<S>::ld(ld_at(plane(src, sp.plane, g.n), sp.idx));
-            gm[p + 1] = Conv<S>::ld(ld_at(plane(src, sm.plane, g.n), sm.idx));
+            gp[p + 1] = Conv<S>::ld(ld_slot(src, g, sp));
+            gm[p + 1] = Conv<S>::ld(ld_slot(src, g, sm));
         }
         C drho, jx, jy, jz;
         moments_of<LAT>(gp, gm, drho, jx, jy, jz);
@@ -486,13 +487,13 @@ __global__ __launch_bounds__(256) void k_seed(const S *__restrict__ src, typenam
             jv = 0.5 * ((double)mx * mx + (double)my * my + (double)mz * mz) / (double)rho;
         }
         // lam_i = base + u . c_i
-        st_at(plane(lam, 0, g.n), c.own, base);
+        st_pop(lam, g, 0, own_ref(c), base);
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
             const PairRow v = L::pair(p);
             const C uc = (C)v.cx * ux + (C)v.cy * uy + (C)v.cz * uz;
-            st_at(plane(lam, 2 * p + 1, g.n), c.own, base + uc);
-            st_at(plane(lam, 2 * p + 2, g.n), c.own, base - uc);
+            st_pop(lam, g, 2 * p + 1, own_ref(c), base + uc);
+            st_pop(lam, g, 2 * p + 2, own_ref(c), base - uc);
         }
     }
     red[tid] = jv;
@@ -510,14 +511,14 @@ __global__ __launch_bounds__(256) void k_seed(const S *__restrict__ src, typenam
 // link word's bit for direction i marks x - c_i solid, so x + c is bit 2p+2 and x - c bit 2p+1.
 template <int LAT> __device__ inline Slot adjoint_slot_plus(const Cell &c, int p, uint32_t links)
 {
-    if (links >> (2 * p + 2) & 1u) return Slot{2 * p + 2, c.own};
-    return Slot{2 * p + 1, src_minus<LAT>(c, p)};
+    const bool bounce = (links >> (2 * p + 2) & 1u) != 0u;
+    return Slot{bounce, same_z(c, Lattice<LAT>::pair(p).cz), 2 * p + 2, 2 * p + 1, own_ref(c), src_minus<LAT>(c, p)};
 }
 
 template <int LAT> __device__ inline Slot adjoint_slot_minus(const Cell &c, int p, uint32_t links)
 {
-    if (links >> (2 * p + 1) & 1u) return Slot{2 * p + 1, c.own};
-    return Slot{2 * p + 2, src_plus<LAT>(c, p)};
+    const bool bounce = (links >> (2 * p + 1) & 1u) != 0u;
+    return Slot{bounce, same_z(c, Lattice<LAT>::pair(p).cz), 2 * p + 1, 2 * p + 2, own_ref(c), src_plus<LAT>(c, p)};
 }
 
 // One reverse step: lam_in = lam(t+1) (canonical), state = the buffer whose gather gives f(t);
@@ -547,16 +548,16 @@ __global__ __launch_bounds__(256) void k_adjoint(const S *__restrict__ state, co
     if (inside && (lk & 1u)) {
         // a solid cell holds no state: its adjoint is zero and it adds no sensitivity
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i) st_at(plane(lam_out, i, g.n), c.own, C(0));
+        for (int i = 0; i < L::Q; ++i) st_pop(lam_out, g, i, own_ref(c), C(0));
     } else if (inside) {
         // forward quantities at x (the canonical gather, bounce-back slots included)
         C gp[NP + 1], gm[NP + 1];
-        gp[0] = Conv<S>::ld(ld_at(plane(state, 0, g.n), c.own));
+        gp[0] = Conv<S>::ld(ld_pop(state, g, 0, own_ref(c)));
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
             const Slot sp = slot_plus<LAT>(c, p, lk), sm = slot_minus<LAT>(c, p, lk);
-            gp[p + 1] = Conv<S>::ld(ld_at(plane(state, sp.plane, g.n), sp.idx));
-            gm[p + 1] = Conv<S>::ld(ld_at(plane(state, sm.plane, g.n), sm.idx));
+            gp[p + 1] = Conv<S>::ld(ld_slot(state, g, sp));
+            gm[p + 1] = Conv<S>::ld(ld_slot(state, g, sm));
         }
         C drho, jx, jy, jz;
         moments_of<LAT>(gp, gm, drho, jx, jy, jz);
@@ -566,12 +567,12 @@ __global__ __launch_bounds__(256) void k_adjoint(const S *__restrict__ state, co
         // adjoint of the post-collision populations: mu_k(x) = lam_k(t+1, x + c_k), or, when
         // x + c_k is solid (halfway bounce-back), lam_opp(k)(t+1, x)
         C mup[NP + 1], mum[NP + 1];
-        mup[0] = ld_at(plane(lam_in, 0, g.n), c.own);
+        mup[0] = ld_pop(lam_in, g, 0, own_ref(c));
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
             const Slot ap = adjoint_slot_plus<LAT>(c, p, lk), am = adjoint_slot_minus<LAT>(c, p, lk);
-            mup[p + 1] = ld_at(plane(lam_in, ap.plane, g.n), ap.idx);
-            mum[p + 1] = ld_at(plane(lam_in, am.plane, g.n), am.idx);
+            mup[p + 1] = ld_slot(lam_in, g, ap);
+            mum[p + 1] = ld_slot(lam_in, g, am);
         }
         const C mg = gray ? (C)gray[c.own] : C(0);
         const C keep = C(1) - mg;  // nu_k = keep * mu_k
@@ -607,7 +608,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const S *__restrict__ state, co
             dtau = (keep * mup[0]) * (eq - gp[0]);
             if constexpr (FORCED) b += eq_rest(k, ef) - eq;
             dm = mup[0] * (gp[0] - b);
-            st_at(plane(lam_out, 0, g.n), c.own, fmad(mg, mup[0], fmad(om, keep * mup[0], base)));
+            st_pop(lam_out, g, 0, own_ref(c), fmad(mg, mup[0], fmad(om, keep * mup[0], base)));
         }
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
@@ -625,8 +626,8 @@ __global__ __launch_bounds__(256) void k_adjoint(const S *__restrict__ state, co
             }
             const PairRow v = L::pair(p);
             const C vc = (C)v.cx * ax + (C)v.cy * ay + (C)v.cz * az;
-            st_at(plane(lam_out, 2 * p + 1, g.n), c.own, fmad(mg, mum[p + 1], fmad(om, keep * mup[p + 1], base + vc)));
-            st_at(plane(lam_out, 2 * p + 2, g.n), c.own, fmad(mg, mup[p + 1], fmad(om, keep * mum[p + 1], base - vc)));
+            st_pop(lam_out, g, 2 * p + 1, own_ref(c), fmad(mg, mum[p + 1], fmad(om, keep * mup[p + 1], base + vc)));
+            st_pop(lam_out, g, 2 * p + 2, own_ref(c), fmad(mg, mup[p + 1], fmad(om, keep * mum[p + 1], base - vc)));
             dm = fmad(mup[p + 1], gm[p + 1] - bp, dm);
             dm = fmad(mum[p + 1], gp[p + 1] - bm, dm);
         }

@@ -136,6 +136,18 @@ def test_size_limit_is_per_plane_bytes():
     assert ei.value.code == lbm.LBM_ERR_SIZE
 
 
+def test_size_limit_of_one_z_plane():
+    # the population layout addresses one z-plane with 32-bit byte offsets: a 2-D grid is one
+    # z-plane, so D2Q9 FP32 stops below 2^32 / (9 x 4) cells
+    ok = lbm.make_params("D2Q9", "f32", (10000, 10000, 1), W.config1_theta(), "theta", 0.7)
+    lbm.lbm_prepare(ok)
+    bad = lbm.make_params("D2Q9", "f32", (11000, 11000, 1), W.config1_theta(), "theta", 0.7)
+    with pytest.raises(lbm.LBMError) as ei:
+        lbm.lbm_prepare(bad)
+    assert ei.value.code == lbm.LBM_ERR_SIZE
+    assert "z-plane" in str(ei.value)
+
+
 def test_sizes():
     p = lbm.make_params("D3Q19", "f32", (256, 256, 256), W.config2_theta(0), "theta", 0.7)
     assert lbm.lbm_pop_bytes(p) == 19 * 256 ** 3 * 4
@@ -205,8 +217,8 @@ def test_batch_layout_queries():
     total, offs = lbm.lbm_batch_cells(p)
     sizes = [int(np.prod(d["shape"])) for d in doms]
     assert total == sum(sizes) and offs == list(np.concatenate([[0], np.cumsum(sizes)]))
-    # one population array: q planes per domain, each rounded up to 128 cells
-    assert lbm.lbm_batch_pop_bytes(p) == sum(19 * ((n + 127) // 128 * 128) * 4 for n in sizes)
+    # one population array: q x cells elements per domain, rounded up to 128 elements
+    assert lbm.lbm_batch_pop_bytes(p) == sum((19 * n + 127) // 128 * 128 * 4 for n in sizes)
     assert lbm.lbm_batch_scratch_bytes(p) > 0
     p16 = lbm.make_batch_params("D3Q19", "f16", doms)
     assert lbm.lbm_batch_pop_bytes(p16) * 2 == lbm.lbm_batch_pop_bytes(p)

@@ -63,6 +63,18 @@ def test_degenerate_grids_fp64(lattice, shape):
     check(wl, "f64", 25)
 
 
+# Population blocks hold the largest divisor of ny rows that keeps one direction plane of a
+# block within 8 KiB: these shapes give one row per block (prime ny, wide rows), several
+# blocks per z-plane, and one block per z-plane, so the y-wrap and block crossings are exercised.
+@pytest.mark.parametrize("lattice,storage,shape", [("D3Q19", "f64", (300, 7, 3)),    # 1 row x 7 blocks
+                                                   ("D3Q27", "f32", (96, 48, 3)),    # 16 rows x 3 blocks
+                                                   ("D2Q9", "f64", (130, 33, 1)),    # 3 rows x 11 blocks
+                                                   ("D3Q19", "f32", (24, 20, 6))])   # 20 rows x 1 block
+def test_blocked_layout_shapes(lattice, storage, shape):
+    wl = _random_wl(lattice, shape, seed=11)
+    check(wl, storage, 20)
+
+
 @pytest.mark.parametrize("kind", ["A", "Atilde"])
 def test_tensor_kinds_fp64(kind):
     rng = np.random.default_rng(3)

@@ -40,6 +40,14 @@ def test_masked_forced_matches_oracle(lattice, shape, storage):
     check(wl, storage, 60)
 
 
+@pytest.mark.parametrize("lattice,storage,shape", [("D3Q19", "f64", (300, 7, 3)), ("D3Q27", "f32", (96, 48, 3)),
+                                                   ("D2Q9", "f64", (130, 33, 1))])
+def test_masked_blocked_layout_shapes(lattice, storage, shape):
+    """Bounce-back slots whose two candidates lie in different population blocks and z-planes."""
+    wl = _masked_wl(lattice, shape, seed=24)
+    check(wl, storage, 20)
+
+
 @pytest.mark.parametrize("lattice", ["D2Q9", "D3Q27"])
 def test_force_without_mask_matches_oracle(lattice):
     shape = (24, 20, 1) if lattice == "D2Q9" else (12, 10, 8)
