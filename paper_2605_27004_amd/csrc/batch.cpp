@@ -26,7 +26,6 @@ namespace {
 
 constexpr int64_t kMaxWorkGroups = 16384;      // persistent grid bound (work-group lists in scratch)
 constexpr int64_t kMaxDomains = 1 << 24;
-constexpr int64_t kDomainAlign = 128;          // elements per domain block granularity: 256 B at 2-byte storage
 constexpr uint32_t kDefaultSpinLimit = 1u << 20;
 
 // Everything that follows from the parameters alone.
@@ -85,10 +84,17 @@ int plan_of(const lbm_batch_params *p, Plan &pl)
         std::memset(&b, 0, sizeof b);
         const int64_t n = (int64_t)pr.n;
         // a domain is addressed with one 32-bit byte offset (tiles may span its z-planes)
-        if ((double)pr.q * (double)n * pr.bytes >= 4294967296.0)
-            return fail(LBM_ERR_SIZE, "domain %lld holds 4 GiB or more of populations", (long long)i);
-        const int64_t elems = (pr.q * n + kDomainAlign - 1) / kDomainAlign * kDomainAlign;
+        // linear blocks of kBlockBytes per direction plane (a power of two >= the 256-cell tile)
+        const int64_t block = kBlockBytes / pr.bytes;
+        int lb = 0;
+        while ((int64_t)1 << lb < block) ++lb;
+        const int64_t elems = (n + block - 1) / block * block * pr.q;
         b.g = grid_of(dm.nx, dm.ny, dm.nz, pr.q, pr.bytes);
+        b.g.lb = (uint32_t)lb;
+        b.g.bc = (uint32_t)block;
+        b.g.bq = (uint32_t)(pr.q * block);
+        if ((double)elems * pr.bytes >= 4294967296.0)
+            return fail(LBM_ERR_SIZE, "domain %lld holds 4 GiB or more of populations", (long long)i);
         b.cells = pr.n;
         b.mx = dm.nx == 1 ? 0xffffffffu : (uint32_t)(4294967296.0 / (double)dm.nx);
         b.my = dm.ny == 1 ? 0xffffffffu : (uint32_t)(4294967296.0 / (double)dm.ny);

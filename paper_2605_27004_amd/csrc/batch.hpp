@@ -2,11 +2,12 @@
 // batched update: many independent periodic domains of uneven sizes, each with its own
 // tensor and relaxation time, advanced together.
 //
-// Storage. Domain d owns a stretch of both population arrays starting at element `base`
-// (q cells elements rounded up to 128, so every domain starts on a 256-byte boundary in every
-// storage type), holding the domain's populations in the blocked layout of its Grid. Host
-// arrays of rho and s concatenate the domains' cells (x fastest) without padding, from cell
-// offset `cell0`.
+// Storage. Domain d owns a stretch of both population arrays starting at element `base`,
+// holding its populations in linear blocks (FlatCell): block b holds canonical cells
+// [b B, (b + 1) B) as q direction planes of B = 2^g.lb cells (8 KiB each), and the last block
+// is padded to B cells, so every domain and every tile of 256 cells starts on a whole cache
+// line in every plane. Host arrays of rho and s concatenate the domains' cells (x fastest)
+// without padding, from cell offset `cell0`.
 //
 // Work units. A tile is 256 consecutive cells of one domain (the last tile of a domain may be
 // short). The step-per-launch mode runs one work-group per tile. The persistent mode hands

@@ -134,37 +134,44 @@ __device__ inline Cell cell_of(const Grid &g, int32_t x, int32_t y, int32_t z)
     return c;
 }
 
-// A cell addressed with one 32-bit index over the whole grid: a batched domain (whose
-// populations stay below 4 GiB), or canonical order for per-cell arrays (canon_cell_of).
+// A cell of a batched domain, addressed with one 32-bit index over the domain (whose
+// populations stay below 4 GiB). Batched domains use linear blocks instead of row blocks:
+// block b holds cells [b B, (b + 1) B) of the canonical order (B = 2^lb, a multiple of the
+// 256-cell tile), its q direction planes back to back, so canonical cell n of direction i is
+//     (n >> lb) q B + i B + (n mod B).
+// A tile then stores whole cache lines in every plane however short the domain's rows are.
+// With lb = 31 and bq = 0 the same cell addresses canonical order (canon_cell_of).
 struct FlatCell {
     uint32_t own;  // canonical index
-    uint32_t at;   // storage (or canonical) index
+    uint32_t lb;   // log2 of the cells per block
+    uint32_t bq;   // q B: elements per block
     AxisOff ox, oy, oz;
 };
+
+__device__ inline uint32_t lin_at(const FlatCell &c, uint32_t n) { return (n >> c.lb) * c.bq + (n & ((1u << c.lb) - 1u)); }
 
 __device__ inline FlatCell flat_cell_of(const Grid &g, uint32_t x, uint32_t y, uint32_t z)
 {
     FlatCell c;
     c.own = (z * (uint32_t)g.ny + y) * (uint32_t)g.nx + x;
-    c.ox = axis_off(x, (uint32_t)g.nx, 1u);
-    c.at = z * g.zs + row_off(g, y, c.oy) + x;
-    c.oz = axis_off(z, (uint32_t)g.nz, g.zs);
-    return c;
-}
-
-__device__ inline FlatCell canon_cell_of(const Grid &g, uint32_t x, uint32_t y, uint32_t z)
-{
-    FlatCell c;
-    c.own = (z * (uint32_t)g.ny + y) * (uint32_t)g.nx + x;
-    c.at = c.own;
+    c.lb = g.lb;
+    c.bq = g.bq;
     c.ox = axis_off(x, (uint32_t)g.nx, 1u);
     c.oy = axis_off(y, (uint32_t)g.ny, (uint32_t)g.nx);
     c.oz = axis_off(z, (uint32_t)g.nz, (uint32_t)g.nx * (uint32_t)g.ny);
     return c;
 }
 
+__device__ inline FlatCell canon_cell_of(const Grid &g, uint32_t x, uint32_t y, uint32_t z)
+{
+    FlatCell c = flat_cell_of(g, x, y, z);
+    c.lb = 31u;
+    c.bq = 0u;
+    return c;
+}
+
 __device__ inline Ref own_ref(const Cell &c) { return Ref{c.z0, c.at}; }
-__device__ inline Ref own_ref(const FlatCell &c) { return Ref{0u, c.at}; }
+__device__ inline Ref own_ref(const FlatCell &c) { return Ref{0u, lin_at(c, c.own)}; }
 
 // The cell x - c (sign +1) or x + c (sign -1) for velocity c = (cx, cy, cz).
 __device__ inline Ref nbr(const Cell &c, int cx, int cy, int cz)
@@ -173,7 +180,7 @@ __device__ inline Ref nbr(const Cell &c, int cx, int cy, int cz)
 }
 __device__ inline Ref nbr(const FlatCell &c, int cx, int cy, int cz)
 {
-    return Ref{0u, c.at + back(c.ox, cx) + back(c.oy, cy) + back(c.oz, cz)};
+    return Ref{0u, lin_at(c, c.own + back(c.ox, cx) + back(c.oy, cy) + back(c.oz, cz))};
 }
 
 // x - c and x + c for the velocity c of pair p.

@@ -41,8 +41,9 @@ template <typename C> struct StepConsts {
 // consecutive y-rows (rows divides ny), and a block holds its q direction planes one after
 // another, bc = rows nx cells each. Direction i of cell (x, y, z) is element
 //     z zs + (y / rows) bq + i bc + (y mod rows) nx + x,      bq = q bc,  zs = q nx ny.
-// Canonical arrays (masks, link words, per-cell fields, exported populations) keep the plain
-// order x + nx (y + ny z).
+// Batched domains use linear blocks of 2^lb canonical cells instead (bc = 2^lb, bq = q bc;
+// FlatCell). Canonical arrays (masks, link words, per-cell fields, exported populations) keep
+// the plain order x + nx (y + ny z).
 struct Grid {
     int32_t nx, ny, nz;
     uint32_t n;     // cells = nx * ny * nz (< 2^31)
@@ -51,6 +52,7 @@ struct Grid {
     uint32_t bc;    // rows nx: cells per block and direction
     uint32_t bq;    // q bc: elements per block
     uint32_t zs;    // q nx ny: elements per z-plane (the bytes of one z-plane stay below 4 GiB)
+    uint32_t lb;    // batched domains only: log2 of the cells per linear block (bc = 2^lb)
 };
 
 // ---- launchers (kernels.hip) -----------------------------------------------------------

@@ -217,11 +217,12 @@ def test_batch_layout_queries():
     total, offs = lbm.lbm_batch_cells(p)
     sizes = [int(np.prod(d["shape"])) for d in doms]
     assert total == sum(sizes) and offs == list(np.concatenate([[0], np.cumsum(sizes)]))
-    # one population array: q x cells elements per domain, rounded up to 128 elements
-    assert lbm.lbm_batch_pop_bytes(p) == sum((19 * n + 127) // 128 * 128 * 4 for n in sizes)
+    # one population array: per domain, q planes of its cells rounded up to whole blocks of
+    # 8 KiB per direction (2048 FP32 cells, 4096 FP16 cells)
+    assert lbm.lbm_batch_pop_bytes(p) == sum(-(-n // 2048) * 2048 * 19 * 4 for n in sizes)
     assert lbm.lbm_batch_scratch_bytes(p) > 0
     p16 = lbm.make_batch_params("D3Q19", "f16", doms)
-    assert lbm.lbm_batch_pop_bytes(p16) * 2 == lbm.lbm_batch_pop_bytes(p)
+    assert lbm.lbm_batch_pop_bytes(p16) == sum(-(-n // 4096) * 4096 * 19 * 2 for n in sizes)
 
 
 def test_batch_rejects_bad_domains_with_their_index():
