@@ -709,8 +709,20 @@ dim3 cell_grid(const Grid &g, int bx, int by)
     return dim3((uint32_t)((g.nx + bx - 1) / bx), (uint32_t)((g.ny + by - 1) / by), (uint32_t)g.nz);
 }
 
-constexpr int kBlockX = 64;
-constexpr int kBlockY = 4;
+// Work-group shape of every kernel except the step: 256 threads spanning whole x rows where
+// the grid allows (256 x 1, 128 x 2 or 64 x 4), so that each direction's loads and stores of a
+// work-group are full row runs inside one population block.
+dim3 row_block(const Grid &g)
+{
+    const int bx = g.nx > 128 ? 256 : (g.nx > 64 ? 128 : 64);
+    return dim3((uint32_t)bx, (uint32_t)(256 / bx));
+}
+
+dim3 row_grid(const Grid &g)
+{
+    const dim3 b = row_block(g);
+    return cell_grid(g, (int)b.x, (int)b.y);
+}
 
 }  // namespace
 
@@ -718,7 +730,7 @@ hipError_t launch_links(int lattice, const Grid &g, const uint8_t *mask, uint32_
 {
     return by_lattice(lattice, [&](auto lat) {
         constexpr int LAT = decltype(lat)::value;
-        const dim3 grid = cell_grid(g, kBlockX, kBlockY), block(kBlockX, kBlockY);
+        const dim3 grid = row_grid(g), block = row_block(g);
         hipLaunchKernelGGL((k_links<LAT>), grid, block, 0, stream, mask, links, g);
         return hipGetLastError();
     });
@@ -731,7 +743,7 @@ hipError_t launch_init(int lattice, int storage, int order, const Grid &g, const
         return by_storage(storage, [&](auto sv) {
             using S = decltype(sv);
             constexpr int LAT = decltype(lat)::value;
-            const dim3 grid = cell_grid(g, kBlockX, kBlockY), block(kBlockX, kBlockY);
+            const dim3 grid = row_grid(g), block = row_block(g);
             if (order == 2)
                 hipLaunchKernelGGL((k_init<LAT, S, 2>), grid, block, 0, stream, rho, s, links, (S *)dst, g, k);
             else
@@ -783,7 +795,7 @@ hipError_t launch_step(int lattice, int storage, int order, const Grid &g, const
 
 uint32_t moments_blocks(const Grid &g)
 {
-    const dim3 grid = cell_grid(g, kBlockX, kRedThreads / kBlockX);
+    const dim3 grid = row_grid(g);
     return grid.x * grid.y * grid.z;
 }
 
@@ -795,7 +807,7 @@ hipError_t launch_moments(int lattice, int storage, const Grid &g, const StepCon
         return by_storage(storage, [&](auto sv) {
             using S = decltype(sv);
             constexpr int LAT = decltype(lat)::value;
-            const dim3 grid = cell_grid(g, kBlockX, kRedThreads / kBlockX), block(kBlockX, kRedThreads / kBlockX);
+            const dim3 grid = row_grid(g), block = row_block(g);
             hipLaunchKernelGGL((k_moments<LAT, S>), grid, block, 0, stream, (const S *)src, links, rho, s, partials, g,
                                k);
             hipError_t e = hipGetLastError();
@@ -814,7 +826,7 @@ hipError_t launch_permute(int lattice, int storage, int mode, const Grid &g, con
         return by_storage(storage, [&](auto sv) {
             using S = decltype(sv);
             constexpr int LAT = decltype(lat)::value;
-            const dim3 grid = cell_grid(g, kBlockX, kBlockY), block(kBlockX, kBlockY);
+            const dim3 grid = row_grid(g), block = row_block(g);
             if (mode == 0)
                 hipLaunchKernelGGL((k_permute<LAT, S, 0>), grid, block, 0, stream, src, dst, links, g, k);
             else if (mode == 1)
@@ -837,7 +849,7 @@ hipError_t launch_seed(int lattice, int storage, const Grid &g, const StepConsts
             constexpr int LAT = decltype(lat)::value;
             const StepConsts<C> *kc;
             if constexpr (sizeof(C) == 8) kc = &k64; else kc = &k32;
-            const dim3 grid = cell_grid(g, kBlockX, kRedThreads / kBlockX), block(kBlockX, kRedThreads / kBlockX);
+            const dim3 grid = row_grid(g), block = row_block(g);
             hipLaunchKernelGGL((k_seed<LAT, S>), grid, block, 0, stream, (const S *)src, (C *)lam, jpart, g, *kc, kind,
                                plane, links);
             return hipGetLastError();
@@ -856,7 +868,7 @@ hipError_t launch_adjoint(int lattice, int storage, int order, const Grid &g, co
             constexpr int LAT = decltype(lat)::value;
             const StepConsts<C> *kc;
             if constexpr (sizeof(C) == 8) kc = &k64; else kc = &k32;
-            const dim3 grid = cell_grid(g, kBlockX, kRedThreads / kBlockX), block(kBlockX, kRedThreads / kBlockX);
+            const dim3 grid = row_grid(g), block = row_block(g);
 #define LBM_ADJ(O, F)                                                                                            \
     hipLaunchKernelGGL((k_adjoint<LAT, S, O, F>), grid, block, 0, stream, (const S *)state, (const C *)lam_in,     \
                        (C *)lam_out, gray, links, dmask, gpart, g, *kc)
