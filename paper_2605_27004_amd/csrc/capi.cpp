@@ -520,7 +520,7 @@ int grad_layout(const lbm_ctx *c, const lbm_grad_spec *spec, GradLayout &l)
                     (long long)(c->p.nx - 1));
     const int64_t popb = (int64_t)c->pr.q * c->grid.n * c->pr.bytes;
     const int64_t lamb = (int64_t)c->pr.q * c->grid.n * (c->p.storage == LBM_F64 ? 8 : 4);
-    const int64_t nb = moments_blocks(c->grid);
+    const int64_t nb = moments_blocks(c->grid), na = adjoint_blocks(c->grid);
     l.seglen = std::min<int64_t>(spec->checkpoint_every, std::max<int64_t>(spec->nsteps, 1));
     l.nseg = (spec->nsteps + spec->checkpoint_every - 1) / spec->checkpoint_every;
     int64_t off = 0;
@@ -533,7 +533,7 @@ int grad_layout(const lbm_ctx *c, const lbm_grad_spec *spec, GradLayout &l)
     l.lam_b = off;
     off += align256(lamb);
     l.gpart = off;
-    off += align256(8 * kGradPartialsHost * nb);
+    off += align256(8 * kGradPartialsHost * na);
     l.jpart = off;
     off += align256(8 * nb);
     l.sums = off;
@@ -562,7 +562,7 @@ int lbm_grad(lbm_ctx *c, const lbm_grad_spec *spec, void *workspace, double *obj
     char *ws = (char *)workspace;
     const int64_t popb = (int64_t)c->pr.q * c->grid.n * c->pr.bytes;
     const int64_t pstride = align256(popb);
-    const uint32_t nb = moments_blocks(c->grid);
+    const uint32_t nb = moments_blocks(c->grid), na = adjoint_blocks(c->grid);
     hipStream_t st = c->stream;
     hipError_t e = hipSuccess;
     auto ckpt = [&](int64_t s) { return (void *)(ws + l.ckpt + s * pstride); };
@@ -582,7 +582,7 @@ int lbm_grad(lbm_ctx *c, const lbm_grad_spec *spec, void *workspace, double *obj
     e = launch_seed(c->p.lattice, c->p.storage, c->grid, c->k64, c->k32, c->pop[c->cur], lam_in, jpart,
                     spec->objective, (int)spec->outlet_plane, c->links, st);
     if (e == hipSuccess) e = launch_sum(jpart, nb, 1, sums, st);
-    if (e == hipSuccess) e = launch_zero(gpart, (uint64_t)kGradPartialsHost * nb, st);
+    if (e == hipSuccess) e = launch_zero(gpart, (uint64_t)kGradPartialsHost * na, st);
     if (e == hipSuccess && dmask) e = launch_zero(dmask, c->grid.n, st);
     if (e != hipSuccess) return fail_hip(e, "reverse-sweep set-up");
     // reverse sweep, one recomputed segment at a time
@@ -601,7 +601,7 @@ int lbm_grad(lbm_ctx *c, const lbm_grad_spec *spec, void *workspace, double *obj
             std::swap(lam_in, lam_out);
         }
     }
-    e = launch_sum(gpart, nb, kGradPartialsHost, sums + 1, st);
+    e = launch_sum(gpart, na, kGradPartialsHost, sums + 1, st);
     double h[1 + kGradPartialsHost];
     if (e == hipSuccess) e = hipMemcpyAsync(h, sums, sizeof h, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);

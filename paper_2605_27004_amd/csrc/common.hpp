@@ -94,6 +94,8 @@ hipError_t launch_moments(int lattice, int storage, const Grid &g, const StepCon
                           const uint32_t *links, const void *src, double *rho, double *s, double *partials,
                           double *totals, hipStream_t stream);
 uint32_t moments_blocks(const Grid &g);
+// Work-groups of one launch_adjoint (the gpart partial sets it adds to).
+uint32_t adjoint_blocks(const Grid &g);
 
 // mode 0: out[i][x] = the state's canonical g_i(x) (raw storage type), mode 1: the inverse,
 // mode 2: out[i][x] = double(g_i(x)) + sigma_i. Solid cells: zeros out / ignored in.

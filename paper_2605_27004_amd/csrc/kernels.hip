@@ -521,27 +521,18 @@ template <int LAT> __device__ inline Slot adjoint_slot_minus(const Cell &c, int 
     return Slot{bounce, same_z(c, Lattice<LAT>::pair(p).cz), 2 * p + 1, 2 * p + 2, own_ref(c), src_plus<LAT>(c, p)};
 }
 
-// One reverse step: lam_in = lam(t+1) (canonical), state = the buffer whose gather gives f(t);
-// writes lam_out = lam(t), adds d m per cell to dmask and the work-group's G / d tau sums to
-// gpart (in the same order every step, so the totals are reproducible).
+// One reverse step at one cell: lam_in = lam(t+1) (canonical), state = the buffer whose gather
+// gives f(t); writes lam(t) at the cell, adds d m to dmask and the cell's G / d tau to G, dtau.
 template <int LAT, typename S, int ORDER, bool FORCED>
-__global__ __launch_bounds__(256) void k_adjoint(const S *__restrict__ state, const typename Conv<S>::C *__restrict__ lam_in,
-                                                 typename Conv<S>::C *__restrict__ lam_out,
-                                                 const float *__restrict__ gray, const uint32_t *__restrict__ links,
-                                                 double *__restrict__ dmask, double *__restrict__ gpart, const Grid g,
-                                                 const StepConsts<typename Conv<S>::C> k)
+__device__ inline void adjoint_cell(const S *__restrict__ state, const typename Conv<S>::C *__restrict__ lam_in,
+                                    typename Conv<S>::C *__restrict__ lam_out, const float *__restrict__ gray,
+                                    const uint32_t *__restrict__ links, double *__restrict__ dmask, const Grid &g,
+                                    const StepConsts<typename Conv<S>::C> &k, int32_t x, int32_t y, int32_t z,
+                                    typename Conv<S>::C *G, typename Conv<S>::C &dtau)
 {
     using L = Lattice<LAT>;
     using C = typename Conv<S>::C;
     constexpr int NP = L::NP;
-    constexpr int kWaves = 256 / 64;
-    __shared__ double red[kGradPartials][kWaves];
-    const int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int32_t y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int32_t z = blockIdx.z;
-    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
-    C G[9] = {C(0), C(0), C(0), C(0), C(0), C(0), C(0), C(0), C(0)};
-    C dtau = C(0);
     const bool inside = x < g.nx && y < g.ny;
     const Cell c = cell_of(g, inside ? x : 0, inside ? y : 0, z);
     const uint32_t lk = (inside && links) ? links[c.own] : 0u;
@@ -634,11 +625,42 @@ __global__ __launch_bounds__(256) void k_adjoint(const S *__restrict__ state, co
         dtau *= -w * w;
         if (dmask) dmask[c.own] += (double)dm;
     }
-    // work-group sums of G and d tau: within each wave by lane exchange, then across the waves
+}
+
+// One reverse step over the grid. Work-group (bx, by) takes tile column bx of the rows
+// [by per, (by + 1) per) of the flattened (y-tile, z) order; each lane accumulates its cells'
+// G / d tau in FP64 and the work-group adds its sums to gpart (in the same order every step,
+// so the totals are reproducible).
+template <int LAT, typename S, int ORDER, bool FORCED>
+__global__ __launch_bounds__(256) void k_adjoint(const S *__restrict__ state, const typename Conv<S>::C *__restrict__ lam_in,
+                                                 typename Conv<S>::C *__restrict__ lam_out,
+                                                 const float *__restrict__ gray, const uint32_t *__restrict__ links,
+                                                 double *__restrict__ dmask, double *__restrict__ gpart, const Grid g,
+                                                 const StepConsts<typename Conv<S>::C> k, const uint32_t per)
+{
+    using C = typename Conv<S>::C;
+    constexpr int kWaves = 256 / 64;
+    __shared__ double red[kGradPartials][kWaves];
+    const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    const uint32_t tiles_y = ((uint32_t)g.ny + blockDim.y - 1u) / blockDim.y;
+    const uint32_t rows = tiles_y * (uint32_t)g.nz;
+    const uint32_t f0 = blockIdx.y * per;
+    const uint32_t f1 = f0 + per < rows ? f0 + per : rows;
     double v[kGradPartials];
 #pragma unroll
-    for (int e = 0; e < 9; ++e) v[e] = (double)G[e];
-    v[9] = (double)dtau;
+    for (int e = 0; e < kGradPartials; ++e) v[e] = 0.0;
+    for (uint32_t f = f0; f < f1; ++f) {
+        const int32_t z = (int32_t)(f / tiles_y);
+        const int32_t x = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+        const int32_t y = (int32_t)((f % tiles_y) * blockDim.y + threadIdx.y);
+        C G[9] = {C(0), C(0), C(0), C(0), C(0), C(0), C(0), C(0), C(0)};
+        C dtau = C(0);
+        adjoint_cell<LAT, S, ORDER, FORCED>(state, lam_in, lam_out, gray, links, dmask, g, k, x, y, z, G, dtau);
+#pragma unroll
+        for (int e = 0; e < 9; ++e) v[e] += (double)G[e];
+        v[9] += (double)dtau;
+    }
+    // work-group sums of G and d tau: within each wave by lane exchange, then across the waves
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
@@ -651,7 +673,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const S *__restrict__ state, co
         double t = red[tid][0];
 #pragma unroll
         for (int wv = 1; wv < kWaves; ++wv) t += red[tid][wv];
-        const uint32_t b = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        const uint32_t b = blockIdx.y * gridDim.x + blockIdx.x;
         gpart[kGradPartials * (size_t)b + tid] += t;
     }
 }
@@ -793,6 +815,29 @@ hipError_t launch_step(int lattice, int storage, int order, const Grid &g, const
     });
 }
 
+// Rows (a y-tile of one z-plane) per work-group of the adjoint launch: up to 4, enough to
+// amortise the FP64 work-group reduction of the sensitivities over several cells per lane,
+// while keeping at least 2048 work-groups (8 per compute unit) where the grid has them.
+uint32_t adjoint_rows_per_group(const Grid &g)
+{
+    const dim3 t = row_grid(g);
+    const uint32_t per = t.x * t.y * t.z / 2048u;
+    return per < 1u ? 1u : (per > 4u ? 4u : per);
+}
+
+dim3 adjoint_grid(const Grid &g)
+{
+    const dim3 t = row_grid(g);
+    const uint32_t rows = t.y * t.z, per = adjoint_rows_per_group(g);
+    return dim3(t.x, (rows + per - 1u) / per, 1u);
+}
+
+uint32_t adjoint_blocks(const Grid &g)
+{
+    const dim3 grid = adjoint_grid(g);
+    return grid.x * grid.y;
+}
+
 uint32_t moments_blocks(const Grid &g)
 {
     const dim3 grid = row_grid(g);
@@ -868,10 +913,11 @@ hipError_t launch_adjoint(int lattice, int storage, int order, const Grid &g, co
             constexpr int LAT = decltype(lat)::value;
             const StepConsts<C> *kc;
             if constexpr (sizeof(C) == 8) kc = &k64; else kc = &k32;
-            const dim3 grid = row_grid(g), block = row_block(g);
+            const dim3 grid = adjoint_grid(g), block = row_block(g);
+            const uint32_t per = adjoint_rows_per_group(g);
 #define LBM_ADJ(O, F)                                                                                            \
     hipLaunchKernelGGL((k_adjoint<LAT, S, O, F>), grid, block, 0, stream, (const S *)state, (const C *)lam_in,     \
-                       (C *)lam_out, gray, links, dmask, gpart, g, *kc)
+                       (C *)lam_out, gray, links, dmask, gpart, g, *kc, per)
             if (order == 2) {
                 if (kc->forced) LBM_ADJ(2, true); else LBM_ADJ(2, false);
             } else {
