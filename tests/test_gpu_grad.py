@@ -136,6 +136,43 @@ def test_adjoint_matches_gpu_finite_differences_no_force():
     assert abs(dt[0][1] - fd) <= 1e-6 * abs(fd) + 1e-9 * abs(j)
 
 
+def test_multi_row_adjoint_launch_matches_gpu_finite_differences():
+    """A grid large enough that each adjoint work-group takes several rows (70 x 130 x 67: 4355
+    rows of 128 x 2 tiles, 2 per work-group, the last one alone), with force, gray cells and
+    the flux objective: the FP64 gradient against central differences of the FP64 forward."""
+    c = _case("D3Q19", (70, 130, 67), seed=9)
+    steps, ckpt, plane = 12, 5, 69
+    gray = c["gray"].astype(np.float32)
+
+    def sim_for(tensor, tau):
+        p = lbm.make_params(c["lattice"], "f64", c["shape"], tensor, "theta", tau, force=c["force"], shift="weight",
+                            gray=True)
+        return lbm.Simulation(p, c["rho"], c["s"], mask=gray)
+
+    base = sim_for(c["tensor"], c["tau"])
+    snap = base.get_populations()
+    j, dt, du, _ = base.grad("flux", steps, ckpt, plane, want_dmask=False)
+    base.close()
+
+    def J(tensor, tau):
+        sim = sim_for(tensor, tau)
+        sim.set_populations(snap)
+        v = sim.grad("flux", steps, ckpt, plane, want_dmask=False)[0]
+        sim.close()
+        return v
+
+    h = 1e-4
+    fd = (J(c["tensor"], c["tau"] + h) - J(c["tensor"], c["tau"] - h)) / (2 * h)
+    print(f"[grad] multi-row dtau {du:.9e} fd {fd:.9e}", flush=True)
+    assert abs(du - fd) <= 1e-5 * abs(fd) + 1e-9 * abs(j)
+    h = 1e-5
+    tp = c["tensor"].copy(); tm = c["tensor"].copy()
+    tp[1, 2] += h; tp[2, 1] += h; tm[1, 2] -= h; tm[2, 1] -= h
+    fd = (J(tp, c["tau"]) - J(tm, c["tau"])) / (2 * h)
+    print(f"[grad] multi-row dT_yz {dt[1][2]:.9e} fd {fd:.9e}", flush=True)
+    assert abs(dt[1][2] - fd) <= 1e-5 * abs(fd) + 1e-9 * abs(j)
+
+
 @pytest.mark.parametrize("ckpt", [1, 4, 23, 50])
 def test_checkpoint_interval_does_not_change_gradients(ckpt):
     c = _case("D2Q9", (12, 10, 1))
