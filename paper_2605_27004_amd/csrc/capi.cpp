@@ -607,11 +607,12 @@ int lbm_grad(lbm_ctx *c, const lbm_grad_spec *spec, void *workspace, double *obj
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return fail_hip(e, "gradient read-back");
     *objective = h[0];
-    if (dtau) *dtau = h[10];
+    if (dtau) *dtau = h[7];
     if (dtensor) {
         const int d = c->pr.d;
-        double G[9];  // dJ/dK as a general matrix
-        for (int i = 0; i < 9; ++i) G[i] = h[1 + i];
+        // dJ/dK: the symmetric part, which is all that the derivatives below depend on (K and
+        // the caller's tensor are symmetric)
+        const double G[9] = {h[1], h[4], h[5], h[4], h[2], h[6], h[5], h[6], h[3]};
         double D[9] = {0};  // dJ/dT as a general matrix
         if (c->p.tensor_kind == LBM_TENSOR_THETA) {
             for (int i = 0; i < 9; ++i) D[i] = G[i] / kCs2;  // K = T / cs^2 - I

@@ -75,7 +75,7 @@ hipError_t launch_step(int lattice, int storage, int order, const Grid &g, const
                        void *dst, int block_x, int block_y, int flags, hipStream_t stream);
 
 // ---- the gradient path (reverse sweep) ----
-constexpr int kGradPartialsHost = 10;  // per work-group: dJ/dK (9, general matrix), dJ/dtau
+constexpr int kGradPartialsHost = 7;  // per work-group: dJ/dK (6, symmetric part: xx yy zz xy xz yz), dJ/dtau
 // lam: adjoint populations [q][N] in the arithmetic precision of the storage.
 // links: the link words of a masked grid or null.
 hipError_t launch_seed(int lattice, int storage, const Grid &g, const StepConsts<double> &k64,

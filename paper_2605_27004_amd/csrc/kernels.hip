@@ -332,8 +332,10 @@ __global__ __launch_bounds__(256) void k_copy(const u32x4 *__restrict__ src, u32
 // d K += a G_s(nu) [+ G_s'(nu)], d m += sum_k mu_k (f_opp(k) - b_k). All formulas are in terms
 // of f; the stored deviations differ from f by constants, which cancel in every difference.
 
-// A0, A_a and the K-sensitivity G (9 entries, K treated as a general matrix; add coef * G)
-// of sum_k nu_k f^eq_k(rho, s) for f^eq_k = rho r_k + w_k rho P'_k(s), nu_k = keep * mu_k.
+// A0, A_a and the K-sensitivity G of sum_k nu_k f^eq_k(rho, s) for f^eq_k = rho r_k +
+// w_k rho P'_k(s), nu_k = keep * mu_k. K is symmetric and every tensor gradient the library
+// reports depends on G only through G + G^T, so G holds the symmetric part (G_ab + G_ba) / 2
+// as 6 entries xx, yy, zz, xy, xz, yz; add coef * G.
 template <int LAT, int ORDER, typename C>
 __device__ inline void equilibrium_vjp(const StepConsts<C> &k, C rho, C sx, C sy, C sz, const C *mup, const C *mum,
                                        C keep, C &A0, C &Ax, C &Ay, C &Az, C coef, C *G)
@@ -418,25 +420,25 @@ __device__ inline void equilibrium_vjp(const StepConsts<C> &k, C rho, C sx, C sy
     Ax = rho * Aa[0];
     Ay = rho * Aa[1];
     Az = rho * Aa[2];
-    // G_ab = rho [1.5 T_ab - 0.5 d_ab T0 + 4.5 U_ab - 1.5 d_ab U0 - 3 S3_a s_b] (the U, S3 terms at order 3)
-    const int ie[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+    // G_ab = rho [1.5 T_ab - 0.5 d_ab T0 + 4.5 U_ab - 1.5 d_ab U0 - 3 S3_a s_b] (the U, S3 terms
+    // at order 3); only the last term is not symmetric, and enters as -1.5 (S3_a s_b + S3_b s_a)
+    const int ea[6] = {0, 1, 2, 0, 0, 1}, eb[6] = {0, 1, 2, 1, 2, 2};
     const C rc = rho * coef;
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-        for (int b = 0; b < 3; ++b) {
-            C t = C(1.5) * T[ie[a][b]];
-            if (a == b) t -= C(0.5) * T0;
-            if constexpr (ORDER == 3) {
-                t = fmad(C(4.5), U[ie[a][b]], t);
-                if (a == b) t -= C(1.5) * U0;
-                t -= C(3) * S3[a] * s[b];
-            }
-            G[3 * a + b] = fmad(rc, t, G[3 * a + b]);
+    for (int e = 0; e < 6; ++e) {
+        const int a = ea[e], b = eb[e];
+        C t = C(1.5) * T[e];
+        if (a == b) t -= C(0.5) * T0;
+        if constexpr (ORDER == 3) {
+            t = fmad(C(4.5), U[e], t);
+            if (a == b) t -= C(1.5) * U0;
+            t -= C(1.5) * fmad(S3[a], s[b], S3[b] * s[a]);
         }
+        G[e] = fmad(rc, t, G[e]);
+    }
 }
 
-constexpr int kGradPartials = 10;  // G (9) and d tau, per work-group
+constexpr int kGradPartials = 7;  // symmetric G (6) and d tau, per work-group
 
 // Seed of the reverse sweep from the final state: lam_i = dJ / d f_i, and the objective's
 // per-work-group partial sums. kind 0: flux through the plane x = plane, J = sum (j_x + F_x/2);
@@ -653,12 +655,12 @@ __global__ __launch_bounds__(256) void k_adjoint(const S *__restrict__ state, co
         const int32_t z = (int32_t)(f / tiles_y);
         const int32_t x = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
         const int32_t y = (int32_t)((f % tiles_y) * blockDim.y + threadIdx.y);
-        C G[9] = {C(0), C(0), C(0), C(0), C(0), C(0), C(0), C(0), C(0)};
+        C G[6] = {C(0), C(0), C(0), C(0), C(0), C(0)};
         C dtau = C(0);
         adjoint_cell<LAT, S, ORDER, FORCED>(state, lam_in, lam_out, gray, links, dmask, g, k, x, y, z, G, dtau);
 #pragma unroll
-        for (int e = 0; e < 9; ++e) v[e] += (double)G[e];
-        v[9] += (double)dtau;
+        for (int e = 0; e < 6; ++e) v[e] += (double)G[e];
+        v[6] += (double)dtau;
     }
     // work-group sums of G and d tau: within each wave by lane exchange, then across the waves
 #pragma unroll
