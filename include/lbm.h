@@ -20,7 +20,9 @@
  *    opposite pairs c_{2p-1} = -c_{2p}: axes, face diagonals, body diagonals).
  *  - Fields: rho is FP64 [N]; s (lattice velocity) is FP64 [d][N] (structure of arrays).
  *  - Populations are stored as deviations g_i = f_i - sigma_i from a constant shift sigma_i
- *    (lbm_params.shift_kind) in the storage precision, structure of arrays [q][N].
+ *    (lbm_params.shift_kind) in the storage precision. The two state buffers use a private
+ *    blocked layout (q * N elements, no padding); lbm_get_populations / lbm_set_populations
+ *    exchange the canonical structure of arrays [q][N].
  *    The canonical state at integer t is the PRE-collision f_i(t, x) of eq:LBE_BGK; every
  *    read-out call refers to it, whatever the library keeps internally.
  *  - Device pointers are HIP device addresses owned by the caller; they must stay valid
@@ -51,7 +53,10 @@ extern "C" {
 #define LBM_ERR_HIP (-5)         /* a HIP runtime call failed (message has its string)   */
 #define LBM_ERR_UNSUPPORTED (-6) /* valid request the library does not implement        */
 #define LBM_ERR_NONFINITE (-7)   /* a conservation total is NaN or infinite              */
-#define LBM_ERR_SIZE (-8)        /* grid too large for the library's 32-bit cell indices */
+#define LBM_ERR_SIZE (-8)        /* grid too large: 2^31 cells or more, 4 GiB or more of
+                                    populations in one z-plane (a whole D2Q9 grid is one
+                                    z-plane) or in one batched domain, or a storage-type plane
+                                    of 4 GiB or more                                          */
 
 /* ---- enumerations --------------------------------------------------------------------- */
 #define LBM_D2Q9 0

@@ -76,7 +76,8 @@ hipError_t launch_step(int lattice, int storage, int order, const Grid &g, const
 
 // ---- the gradient path (reverse sweep) ----
 constexpr int kGradPartialsHost = 7;  // per work-group: dJ/dK (6, symmetric part: xx yy zz xy xz yz), dJ/dtau
-// lam: adjoint populations [q][N] in the arithmetic precision of the storage.
+// lam: adjoint populations (q N elements, the population layout of Grid) in the arithmetic
+// precision of the storage.
 // links: the link words of a masked grid or null.
 hipError_t launch_seed(int lattice, int storage, const Grid &g, const StepConsts<double> &k64,
                        const StepConsts<float> &k32, const void *src, void *lam, double *jpart, int kind, int plane,
