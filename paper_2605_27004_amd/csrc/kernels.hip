@@ -297,8 +297,10 @@ __global__ __launch_bounds__(256) void k_permute(const void *__restrict__ in, vo
         } else if constexpr (MODE == 1) {
             if (!solid) st_slot((S *)out, g, sl, ld_at(plane((const S *)in, i, g.n), c.own));
         } else {
+            // FP64 output: 8 bytes per cell, so 64-bit indexing (the storage-type planes above
+            // stay below 4 GiB, this one need not)
             const double v = solid ? 0.0 : (double)Conv<S>::ld(ld_slot((const S *)in, g, sl)) + sigma;
-            st_at(plane((double *)out, i, g.n), c.own, v);
+            ((double *)out)[(size_t)i * g.n + c.own] = v;
         }
     };
     move(0, fixed_slot(0, own_ref(c)), k.sigma[0]);

@@ -75,6 +75,31 @@ def test_blocked_layout_shapes(lattice, storage, shape):
     check(wl, storage, 20)
 
 
+def test_fp64_export_of_a_grid_beyond_2_29_cells():
+    """lbm_get_f64 of an FP16 grid with more than 2^29 cells: each FP64 direction plane of the
+    export then exceeds 4 GiB, which the export must address with 64-bit offsets. At rest the
+    state stays the rest equilibrium, so every sampled cell (below and above 2^29) reads back
+    the same populations, with density 1."""
+    shape = (1024, 1024, 513)
+    n = int(np.prod(shape))
+    assert n > 2 ** 29
+    rho, s = W.uniform_fields(shape, 3)
+    p = lbm.make_params("D3Q19", "f16", shape, W.config2_theta(0), "theta", 0.7)
+    sim = lbm.Simulation(p, rho, s)
+    del rho, s
+    sim.step(1)
+    f = sim.f64()
+    cells = torch.tensor([0, 2 ** 29 - 1, 2 ** 29, 2 ** 29 + 777, n - 1], device=f.device)
+    got = f[:, cells].cpu().numpy()
+    print(f"[parity] export beyond 2^29 cells: {got[:3, :].tolist()}", flush=True)
+    del f
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    assert np.array_equal(got, np.repeat(got[:, :1], len(cells), axis=1))
+    assert abs(got.sum(axis=0) - 1.0).max() < 1e-12
+
+
 @pytest.mark.parametrize("kind", ["A", "Atilde"])
 def test_tensor_kinds_fp64(kind):
     rng = np.random.default_rng(3)
