@@ -220,7 +220,8 @@ typedef struct lbm_grad_spec {
 
 /* Device workspace lbm_grad needs for this context and spec (checkpoints, one segment of
  * recomputed states, two adjoint buffers, partial sums); a negative LBM_ERR_* code when the
- * request is invalid or unsupported. */
+ * request is invalid or unsupported. LBM_ERR_SIZE when one z-plane of the adjoint
+ * populations (q nx ny values in FP32, FP64 for FP64 storage) would reach 4 GiB. */
 int64_t lbm_grad_workspace_bytes(const lbm_ctx *ctx, const lbm_grad_spec *spec);
 
 /*   workspace: device buffer of lbm_grad_workspace_bytes, 256-byte aligned.

@@ -519,7 +519,12 @@ int grad_layout(const lbm_ctx *c, const lbm_grad_spec *spec, GradLayout &l)
         return fail(LBM_ERR_ARG, "outlet_plane %lld outside 0..%lld", (long long)spec->outlet_plane,
                     (long long)(c->p.nx - 1));
     const int64_t popb = (int64_t)c->pr.q * c->grid.n * c->pr.bytes;
-    const int64_t lamb = (int64_t)c->pr.q * c->grid.n * (c->p.storage == LBM_F64 ? 8 : 4);
+    const int lam_bytes = c->p.storage == LBM_F64 ? 8 : 4;
+    const int64_t lamb = (int64_t)c->pr.q * c->grid.n * lam_bytes;
+    // the adjoint populations use the state's layout in the arithmetic precision (FP32 for
+    // half storage), and one z-plane of them must stay below 4 GiB as well
+    if ((double)c->pr.q * (double)c->p.nx * (double)c->p.ny * lam_bytes >= 4294967296.0)
+        return fail(LBM_ERR_SIZE, "one z-plane of the adjoint populations would hold 4 GiB or more");
     const int64_t nb = moments_blocks(c->grid), na = adjoint_blocks(c->grid);
     l.seglen = std::min<int64_t>(spec->checkpoint_every, std::max<int64_t>(spec->nsteps, 1));
     l.nseg = (spec->nsteps + spec->checkpoint_every - 1) / spec->checkpoint_every;

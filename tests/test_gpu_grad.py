@@ -1,5 +1,7 @@
 """Gradients by the hand-written adjoint (lbm_grad) against central finite differences of the
 FP64 oracle (the brute-force reference) and of the library's own FP64 forward."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -171,6 +173,22 @@ def test_multi_row_adjoint_launch_matches_gpu_finite_differences():
     fd = (J(tp, c["tau"]) - J(tm, c["tau"])) / (2 * h)
     print(f"[grad] multi-row dT_yz {dt[1][2]:.9e} fd {fd:.9e}", flush=True)
     assert abs(dt[1][2] - fd) <= 1e-5 * abs(fd) + 1e-9 * abs(j)
+
+
+def test_grad_rejects_an_adjoint_z_plane_beyond_4gib():
+    """FP16 storage of an 11000^2 D2Q9 grid passes the z-plane limit (9 x 2 bytes per cell),
+    but its FP32 adjoint populations would not (9 x 4 bytes): lbm_grad_workspace_bytes
+    reports LBM_ERR_SIZE instead of letting the kernels' 32-bit offsets wrap."""
+    shape = (11000, 11000, 1)
+    rho, s = W.uniform_fields(shape, 2)
+    p = lbm.make_params("D2Q9", "f16", shape, W.config1_theta(), "theta", 0.8)
+    sim = lbm.Simulation(p, rho, s)
+    spec = lbm.make_grad_spec("kinetic_energy", 10, 5, 0)
+    rc = lbm._lib.lbm_grad_workspace_bytes(sim.ctx, ctypes.byref(spec))
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    assert rc == lbm.LBM_ERR_SIZE
 
 
 @pytest.mark.parametrize("ckpt", [1, 4, 23, 50])
