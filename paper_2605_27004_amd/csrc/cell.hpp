@@ -173,7 +173,7 @@ __device__ inline FlatCell canon_cell_of(const Grid &g, uint32_t x, uint32_t y, 
 __device__ inline Ref own_ref(const Cell &c) { return Ref{c.z0, c.at}; }
 __device__ inline Ref own_ref(const FlatCell &c) { return Ref{0u, lin_at(c, c.own)}; }
 
-// The cell x - c (sign +1) or x + c (sign -1) for velocity c = (cx, cy, cz).
+// The cell x - (cx, cy, cz), periodic (src_plus passes the pair's c, src_minus its -c).
 __device__ inline Ref nbr(const Cell &c, int cx, int cy, int cz)
 {
     return Ref{cz > 0 ? c.zm : (cz < 0 ? c.zp : c.z0), c.at + back(c.ox, cx) + back(c.oy, cy)};
