@@ -66,18 +66,21 @@ def _batch_f(b, full, i):
     return b.domain_f64(full, i).cpu().numpy()
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
-def test_batch_equals_single_domain_runs_bitwise(storage):
-    doms = _small_batch()
+@pytest.mark.parametrize("lattice,storage", [("D3Q19", "f64"), ("D3Q19", "f32"), ("D3Q19", "f16"), ("D3Q19", "bf16"),
+                                             ("D2Q9", "f32"), ("D3Q27", "f16")])
+def test_batch_equals_single_domain_runs_bitwise(lattice, storage):
+    """Every batched domain (linear population blocks) against the same domain run alone (row
+    blocks): the arithmetic is shared, so the results are bitwise equal in every storage."""
+    doms = _small_batch(lattice=lattice, edges=(1, 40) if lattice == "D2Q9" else (1, 21))
     steps = 23
-    print(f"[batch] bitwise {storage} {len(doms)} domains, {steps} steps", flush=True)
-    b = lbm.Batch("D3Q19", storage, doms)
+    print(f"[batch] bitwise {lattice} {storage} {len(doms)} domains, {steps} steps", flush=True)
+    b = lbm.Batch(lattice, storage, doms)
     b.step(steps)
     full = b.f64()
     torch.cuda.synchronize()
     assert b.t == steps
     for i, dm in enumerate(doms):
-        ref = _single(dm, "D3Q19", storage, steps)
+        ref = _single(dm, lattice, storage, steps)
         got = _batch_f(b, full, i)
         assert np.array_equal(got, ref), (i, dm["shape"], np.abs(got - ref).max())
     b.close()
