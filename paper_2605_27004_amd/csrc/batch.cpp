@@ -84,8 +84,8 @@ int plan_of(const lbm_batch_params *p, Plan &pl)
         std::memset(&b, 0, sizeof b);
         const int64_t n = (int64_t)pr.n;
         // a domain is addressed with one 32-bit byte offset (tiles may span its z-planes)
-        // linear blocks of kBlockBytes per direction plane (a power of two >= the 256-cell tile)
-        const int64_t block = kBlockBytes / pr.bytes;
+        // linear blocks of block_bytes per direction plane (a power of two >= the 256-cell tile)
+        const int64_t block = block_bytes(pr.bytes) / pr.bytes;
         int lb = 0;
         while ((int64_t)1 << lb < block) ++lb;
         const int64_t elems = (n + block - 1) / block * block * pr.q;

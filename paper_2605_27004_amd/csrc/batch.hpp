@@ -4,7 +4,7 @@
 //
 // Storage. Domain d owns a stretch of both population arrays starting at element `base`,
 // holding its populations in linear blocks (FlatCell): block b holds canonical cells
-// [b B, (b + 1) B) as q direction planes of B = 2^g.lb cells (8 KiB each), and the last block
+// [b B, (b + 1) B) as q direction planes of B = 2^g.lb cells (8 KiB each, 32 KiB in FP64), and the last block
 // is padded to B cells, so every domain and every tile of 256 cells starts on a whole cache
 // line in every plane. Host arrays of rho and s concatenate the domains' cells (x fastest)
 // without padding, from cell offset `cell0`.

@@ -142,7 +142,7 @@ Grid grid_of(int64_t nx, int64_t ny, int64_t nz, int q, int bytes)
     g.n = (uint32_t)(nx * ny * nz);
     int64_t rows = 1;
     for (int64_t r = ny; r >= 1; --r)
-        if (ny % r == 0 && r * nx * bytes <= kBlockBytes) {
+        if (ny % r == 0 && r * nx * bytes <= block_bytes(bytes)) {
             rows = r;
             break;
         }

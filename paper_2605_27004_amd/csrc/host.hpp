@@ -48,10 +48,11 @@ int prepare(const lbm_params *p, Prepared &out);
 template <typename C> StepConsts<C> consts_for(const lbm_params &p, const Prepared &pr);
 
 // Target bytes of one direction plane of one block in the population layout (Grid): rows per
-// block is the largest divisor of ny with rows * nx * bytes <= kBlockBytes, at least 1.
+// block is the largest divisor of ny with rows * nx * bytes <= block_bytes(bytes), at least 1.
 // Blocks of about this size keep a work-group's 2q population streams within one compact
-// stretch of memory; measured on the D3Q19 step, 8 KiB was best for FP32.
-constexpr int64_t kBlockBytes = 8192;
+// stretch of memory; measured on the D3Q19 256^3 step, 8 KiB was best for FP32 and FP16,
+// 32 KiB for FP64.
+constexpr int64_t block_bytes(int bytes) { return bytes == 8 ? 32768 : 8192; }
 
 // Extents and population layout of an nx x ny x nz grid of q directions in `bytes`-byte
 // storage (the caller has validated the sizes).
