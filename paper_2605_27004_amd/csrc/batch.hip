@@ -45,12 +45,17 @@ __device__ inline void step_cell(const S *__restrict__ src, S *__restrict__ dst,
 {
     using C = typename Conv<S>::C;
     constexpr int NP = Lattice<LAT>::NP;
+    constexpr PullOrder<LAT> kPull{};
     C gp[NP + 1], gm[NP + 1];
-    gp[0] = Conv<S>::ld(ld_pop(src, g, 0, own_ref(c)));
 #pragma unroll
-    for (int p = 0; p < NP; ++p) {
-        gp[p + 1] = Conv<S>::ld(ld_pop(src, g, 2 * p + 1, src_plus<LAT>(c, p)));
-        gm[p + 1] = Conv<S>::ld(ld_pop(src, g, 2 * p + 2, src_minus<LAT>(c, p)));
+    for (int j = 0; j < Lattice<LAT>::Q; ++j) {
+        const int i = kPull.dir[j], p = (i - 1) / 2;
+        if (i == 0)
+            gp[0] = Conv<S>::ld(ld_pop(src, g, 0, own_ref(c)));
+        else if (i & 1)
+            gp[p + 1] = Conv<S>::ld(ld_pop(src, g, i, src_plus<LAT>(c, p)));
+        else
+            gm[p + 1] = Conv<S>::ld(ld_pop(src, g, i, src_minus<LAT>(c, p)));
     }
     collide_cell<LAT, ORDER, false, C, kClose<S>>(k, gp, gm);
     st_pop_stream(dst, g, 0, own_ref(c), Conv<S>::st(gp[0]));

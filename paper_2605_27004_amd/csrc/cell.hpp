@@ -242,6 +242,24 @@ template <typename S> __device__ inline void st_pop_stream(S *base, const Grid &
     st_stream(pop_base(base, g, i, r), r.idx, v);
 }
 
+// Issue order of a cell's q pulls: by source z-plane (z - 1, z, z + 1), then by direction
+// index, which is ascending address order in the population layouts. Direction 2p+1 (+c of
+// pair p) is pulled from x - c and 2p+2 (-c) from x + c. On the bare D3Q19 pattern this order
+// measured 2% faster than pair order (the loads of one wave then walk memory upwards).
+template <int LAT> struct PullOrder {
+    int dir[Lattice<LAT>::Q];
+    __host__ __device__ constexpr PullOrder() : dir()
+    {
+        int k = 0;
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int i = 0; i < Lattice<LAT>::Q; ++i) {
+                const int cz = i == 0 ? 0 : Lattice<LAT>::pair((i - 1) / 2).cz;
+                const int src = i == 0 ? 0 : ((i & 1) ? -cz : cz);
+                if (src == dz) dir[k++] = i;
+            }
+    }
+};
+
 // ---- the collision -----------------------------------------------------------------------
 
 // Per-cell quantities of the folded equilibrium that every velocity pair shares.

@@ -73,6 +73,7 @@ __global__ __launch_bounds__(256) void k_step(const S *__restrict__ src, S *__re
 {
     constexpr bool GENERAL = MODE == kLinks;
     using L = Lattice<LAT>;
+    constexpr PullOrder<LAT> kPull{};
     using C = typename Conv<S>::C;
     constexpr int NP = L::NP;
     const uint32_t t = tile_of(m, blockIdx.x);
@@ -93,21 +94,28 @@ __global__ __launch_bounds__(256) void k_step(const S *__restrict__ src, S *__re
 #pragma unroll
             for (int p = 0; p <= NP; ++p) gp[p] = gm[p] = C(0);
         } else {
-            gp[0] = Conv<S>::ld(ld_pop(src, g, 0, own_ref(c)));
 #pragma unroll
-            for (int p = 0; p < NP; ++p) {
-                const Slot sp = slot_plus<LAT>(c, p, lk), sm = slot_minus<LAT>(c, p, lk);
-                gp[p + 1] = Conv<S>::ld(ld_slot(src, g, sp));
-                gm[p + 1] = Conv<S>::ld(ld_slot(src, g, sm));
+            for (int j = 0; j < L::Q; ++j) {
+                const int i = kPull.dir[j], p = (i - 1) / 2;
+                if (i == 0)
+                    gp[0] = Conv<S>::ld(ld_pop(src, g, 0, own_ref(c)));
+                else if (i & 1)
+                    gp[p + 1] = Conv<S>::ld(ld_slot(src, g, slot_plus<LAT>(c, p, lk)));
+                else
+                    gm[p + 1] = Conv<S>::ld(ld_slot(src, g, slot_minus<LAT>(c, p, lk)));
             }
             collide_cell<LAT, ORDER, true, C, kClose<S>>(k, gp, gm);
         }
     } else {
-        gp[0] = Conv<S>::ld(ld_pop(src, g, 0, own_ref(c)));
 #pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            gp[p + 1] = Conv<S>::ld(ld_pop(src, g, 2 * p + 1, src_plus<LAT>(c, p)));
-            gm[p + 1] = Conv<S>::ld(ld_pop(src, g, 2 * p + 2, src_minus<LAT>(c, p)));
+        for (int j = 0; j < L::Q; ++j) {
+            const int i = kPull.dir[j], p = (i - 1) / 2;
+            if (i == 0)
+                gp[0] = Conv<S>::ld(ld_pop(src, g, 0, own_ref(c)));
+            else if (i & 1)
+                gp[p + 1] = Conv<S>::ld(ld_pop(src, g, i, src_plus<LAT>(c, p)));
+            else
+                gm[p + 1] = Conv<S>::ld(ld_pop(src, g, i, src_minus<LAT>(c, p)));
         }
     }
 
