@@ -342,110 +342,179 @@ __global__ __launch_bounds__(256) void k_copy(const u32x4 *__restrict__ src, u32
 // d K += a G_s(nu) [+ G_s'(nu)], d m += sum_k mu_k (f_opp(k) - b_k). All formulas are in terms
 // of f; the stored deviations differ from f by constants, which cancel in every difference.
 
-// A0, A_a and the K-sensitivity G of sum_k nu_k f^eq_k(rho, s) for f^eq_k = rho r_k +
-// w_k rho P'_k(s), nu_k = keep * mu_k. K is symmetric and every tensor gradient the library
-// reports depends on G only through G + G^T, so G holds the symmetric part (G_ab + G_ba) / 2
-// as 6 entries xx, yy, zz, xy, xz, yz; add coef * G.
-template <int LAT, int ORDER, typename C>
-__device__ inline void equilibrium_vjp(const StepConsts<C> &k, C rho, C sx, C sy, C sz, const C *mup, const C *mum,
-                                       C keep, C &A0, C &Ax, C &Ay, C &Az, C coef, C *G)
+// Moments of nu_k = keep mu_k weighted by w_k over all q directions: M0 = sum w nu,
+// M1_a = sum w nu c_a, M2_ab = sum w nu c_a c_b, and the third moments that are not M1 on these
+// lattices (c_a^3 = c_a): M3_aab = sum w nu c_a^2 c_b (a != b) and M3_xyz. They do not depend
+// on s, so one pass over the directions serves the transposed Jacobian at s and, with a force,
+// at s + F / rho.
+template <typename C> struct NuMoments {
+    C m0;
+    C m1[3];
+    C m2[6];  // xx yy zz xy xz yz
+    C m3[7];  // xxy xxz yyx yyz zzx zzy xyz
+};
+
+template <int LAT, typename C>
+__device__ inline NuMoments<C> nu_moments(const StepConsts<C> &k, const C *mup, const C *mum, C keep)
 {
     using L = Lattice<LAT>;
-    const C usq = fmad(sx, sx, fmad(sy, sy, sz * sz));
-    const C ksx = fmad(k.k[0], sx, fmad(k.k[3], sy, k.k[4] * sz));
-    const C ksy = fmad(k.k[3], sx, fmad(k.k[1], sy, k.k[5] * sz));
-    const C ksz = fmad(k.k[4], sx, fmad(k.k[5], sy, k.k[2] * sz));
-    const C even0 = C(-1.5) * usq;
-    const C bq = C(-4.5) * usq;
-    // rest velocity: u = 0, P' = -1.5 |s|^2, dP'/ds = -3 s
-    const C nu0 = keep * mup[0];
-    const C phi0 = nu0 * k.w[0];
-    A0 = nu0 * fmad(k.w[0], even0, k.rest[0]);
-    C S1[3] = {C(0), C(0), C(0)}, S3[3] = {C(0), C(0), C(0)};
-    C S2 = C(3) * phi0;
-    C T0 = phi0, U0 = C(0);
-    C T[6] = {C(0), C(0), C(0), C(0), C(0), C(0)}, U[6] = {C(0), C(0), C(0), C(0), C(0), C(0)};  // xx yy zz xy xz yz
+    NuMoments<C> m;
+    m.m0 = (keep * mup[0]) * k.w[0];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) m.m1[a] = C(0);
+#pragma unroll
+    for (int e = 0; e < 6; ++e) m.m2[e] = C(0);
+#pragma unroll
+    for (int e = 0; e < 7; ++e) m.m3[e] = C(0);
 #pragma unroll
     for (int p = 0; p < L::NP; ++p) {
         const PairRow v = L::pair(p);
-        C u = C(0), kc = C(0);
-        if (v.cx > 0) { u += sx; kc += ksx; }
-        if (v.cx < 0) { u -= sx; kc -= ksx; }
-        if (v.cy > 0) { u += sy; kc += ksy; }
-        if (v.cy < 0) { u -= sy; kc -= ksy; }
-        if (v.cz > 0) { u += sz; kc += ksz; }
-        if (v.cz < 0) { u -= sz; kc -= ksz; }
-        const C u2 = u * u;
-        const C even = fmad(C(4.5), u2, even0);
-        C odd, Bp, Bm;
-        if constexpr (ORDER == 3) {
-            odd = fmad(u, fmad(C(4.5), u2, k.a[p + 1] + bq), C(-3) * kc);
-            // dP'/ds_a = c_a B - (3 + 9u) s_a - 3 (K c)_a with B = A + 9u - 4.5 |s|^2 + 13.5 u^2
-            // (A = k.a already holds the constant 3 of the linear term)
-            const C be = fmad(C(13.5), u2, k.a[p + 1] + bq);
-            Bp = fmad(C(9), u, be);
-            Bm = fmad(C(-9), u, be);
-        } else {
-            odd = C(3) * u;
-            Bp = fmad(C(9), u, C(3));
-            Bm = fmad(C(-9), u, C(3));
-        }
-        const C w = k.w[p + 1];
-        const C np_ = keep * mup[p + 1], nm_ = keep * mum[p + 1];
-        const C fp = np_ * w, fm = nm_ * w;
-        A0 = fmad(np_, fmad(w, even + odd, k.rest[p + 1]), A0);
-        A0 = fmad(nm_, fmad(w, even - odd, k.rest[p + 1]), A0);
-        const C sum = fp + fm, dif = fp - fm;
-        const C sB = fp * Bp - fm * Bm;  // sum_k phi_k B_k c_k along c
-        if constexpr (ORDER == 3)
-            S2 = fmad(C(9) * u, dif, fmad(C(3), sum, S2));
-        else
-            S2 = fmad(C(3), sum, S2);
-        T0 += sum;
-        U0 = fmad(u, dif, U0);
-        const C ud = u * dif;
-        const int cv[3] = {v.cx, v.cy, v.cz};
+        const C fp = (keep * mup[p + 1]) * k.w[p + 1], fm = (keep * mum[p + 1]) * k.w[p + 1];
+        const C sum = fp + fm, dif = fp - fm;  // even and odd parts of the pair
+        const int c[3] = {v.cx, v.cy, v.cz};
+        m.m0 += sum;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            if (cv[a] > 0) { S1[a] += sB; S3[a] += dif; }
-            if (cv[a] < 0) { S1[a] -= sB; S3[a] -= dif; }
+            if (c[a] > 0) m.m1[a] += dif;
+            if (c[a] < 0) m.m1[a] -= dif;
+            if (c[a] != 0) m.m2[a] += sum;
         }
-        // c_a c_b products are +1, -1 or 0
-        const int cc[6] = {cv[0] * cv[0], cv[1] * cv[1], cv[2] * cv[2], cv[0] * cv[1], cv[0] * cv[2], cv[1] * cv[2]};
+        const int ab[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+#pragma unroll
+        for (int e = 0; e < 3; ++e) {
+            const int cc = c[ab[e][0]] * c[ab[e][1]];
+            if (cc > 0) m.m2[3 + e] += sum;
+            if (cc < 0) m.m2[3 + e] -= sum;
+        }
+        // M3_aab: index 2a + (b > a ? b - 1 : b) over b != a, i.e. xxy xxz yyx yyz zzx zzy
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                if (a == b || c[a] == 0) continue;
+                const int e = 2 * a + (b > a ? b - 1 : b);
+                if (c[b] > 0) m.m3[e] += dif;
+                if (c[b] < 0) m.m3[e] -= dif;
+            }
+        const int cxyz = c[0] * c[1] * c[2];
+        if (cxyz > 0) m.m3[6] += dif;
+        if (cxyz < 0) m.m3[6] -= dif;
+    }
+    return m;
+}
+
+// M3_abc from the stored entries (c_a^3 = c_a makes M3_aaa = M1_a).
+template <typename C> __device__ inline C m3_at(const NuMoments<C> &m, int a, int b, int c)
+{
+    if (a == b && b == c) return m.m1[a];
+    if (a != b && b != c && a != c) return m.m3[6];
+    const int r = (a == b) ? a : (a == c ? a : b);  // the repeated index
+    const int o = (a == b) ? c : (a == c ? b : a);  // the other one
+    return m.m3[2 * r + (o > r ? o - 1 : o)];
+}
+
+// A0 = d/drho, A_a = d/ds_a (times rho) and the K-sensitivity G of sum_k nu_k f^eq_k(rho, s)
+// for f^eq_k = rho r_k + w_k rho P'_k(s), from the nu-moments. With u = c.s, kc = c.(K s),
+// r = w (1 + 1.5 c.K.c - 0.5 tr K) and P' = 4.5 u^2 - 1.5 |s|^2 + u (A - 4.5 |s|^2 + 4.5 u^2)
+// - 3 kc, A = 3 + 4.5 c.K.c - 1.5 tr K (order 3; P' = 4.5 u^2 - 1.5 |s|^2 + 3 u at order 2):
+//   sum nu f^eq / rho = M0 (1 - tr K / 2) + 1.5 K:M2 + 4.5 s.M2.s - 1.5 |s|^2 M0
+//                       + (3 - 1.5 tr K) s.M1 + 4.5 s.(K:M3) - 4.5 |s|^2 s.M1 + 4.5 M3:sss
+//                       - 3 M1.(K s).
+// K is symmetric and every tensor gradient the library reports depends on G only through
+// G + G^T, so G holds the symmetric part (G_ab + G_ba) / 2 as 6 entries xx, yy, zz, xy, xz, yz;
+// add coef * G.
+template <int ORDER, typename C>
+__device__ inline void moment_vjp(const StepConsts<C> &k, const NuMoments<C> &m, C rho, C sx, C sy, C sz, C &A0,
+                                  C &Ax, C &Ay, C &Az, C coef, C *G)
+{
+    const C s[3] = {sx, sy, sz};
+    const C Km[3][3] = {{k.k[0], k.k[3], k.k[4]}, {k.k[3], k.k[1], k.k[5]}, {k.k[4], k.k[5], k.k[2]}};
+    const C M2[3][3] = {{m.m2[0], m.m2[3], m.m2[4]}, {m.m2[3], m.m2[1], m.m2[5]}, {m.m2[4], m.m2[5], m.m2[2]}};
+    const C trK = k.k[0] + k.k[1] + k.k[2];
+    const C usq = fmad(sx, sx, fmad(sy, sy, sz * sz));
+    C M2s[3], sM2s = C(0), sM1 = C(0), KM2 = C(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        M2s[a] = fmad(M2[a][0], s[0], fmad(M2[a][1], s[1], M2[a][2] * s[2]));
+        sM2s = fmad(s[a], M2s[a], sM2s);
+        sM1 = fmad(s[a], m.m1[a], sM1);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) KM2 = fmad(Km[a][b], M2[a][b], KM2);
+    }
+    const C base0 = fmad(C(-0.5) * trK, m.m0, m.m0);  // M0 (1 - tr K / 2)
+    const C g = C(1.5) * fmad(C(-1), trK, C(2));      // 3 - 1.5 tr K
+    C bracket = fmad(C(1.5), KM2, base0);
+    bracket = fmad(C(4.5), sM2s, bracket);
+    bracket = fmad(C(-1.5) * usq, m.m0, bracket);
+    C Aa[3];
+    if constexpr (ORDER == 3) {
+        C KM3[3], M3ss[3], KM1[3], T3 = C(0), sKM3 = C(0), sKM1 = C(0);
+        C M3s[3][3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+                M3s[a][b] = fmad(m3_at(m, a, b, 0), s[0], fmad(m3_at(m, a, b, 1), s[1], m3_at(m, a, b, 2) * s[2]));
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            KM3[a] = C(0);
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) KM3[a] = fmad(Km[b][c], m3_at(m, b, c, a), KM3[a]);
+            M3ss[a] = fmad(M3s[a][0], s[0], fmad(M3s[a][1], s[1], M3s[a][2] * s[2]));
+            T3 = fmad(s[a], M3ss[a], T3);
+            sKM3 = fmad(s[a], KM3[a], sKM3);
+            KM1[a] = fmad(Km[a][0], m.m1[0], fmad(Km[a][1], m.m1[1], Km[a][2] * m.m1[2]));
+            sKM1 = fmad(s[a], KM1[a], sKM1);
+        }
+        bracket = fmad(g, sM1, bracket);
+        bracket = fmad(C(4.5), sKM3, bracket);
+        bracket = fmad(C(-4.5) * usq, sM1, bracket);
+        bracket = fmad(C(4.5), T3, bracket);
+        bracket = fmad(C(-3), sKM1, bracket);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            C t = C(9) * M2s[a];
+            t = fmad(C(-3) * s[a], m.m0, t);
+            t = fmad(g, m.m1[a], t);
+            t = fmad(C(4.5), KM3[a], t);
+            t = fmad(C(-9) * s[a], sM1, t);
+            t = fmad(C(-4.5) * usq, m.m1[a], t);
+            t = fmad(C(13.5), M3ss[a], t);
+            t = fmad(C(-3), KM1[a], t);
+            Aa[a] = t;
+        }
+        const int ea[6] = {0, 1, 2, 0, 0, 1}, eb[6] = {0, 1, 2, 1, 2, 2};
+        const C rc = rho * coef;
 #pragma unroll
         for (int e = 0; e < 6; ++e) {
-            if (cc[e] > 0) { T[e] += sum; U[e] += ud; }
-            if (cc[e] < 0) { T[e] -= sum; U[e] -= ud; }
+            const int a = ea[e], b = eb[e];
+            C t = C(1.5) * M2[a][b];
+            if (a == b) t = fmad(C(-0.5), m.m0, fmad(C(-1.5), sM1, t));
+            t = fmad(C(4.5), M3s[a][b], t);
+            t -= C(1.5) * fmad(m.m1[a], s[b], m.m1[b] * s[a]);
+            G[e] = fmad(rc, t, G[e]);
+        }
+    } else {
+        bracket = fmad(C(3), sM1, bracket);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) Aa[a] = fmad(C(9), M2s[a], fmad(C(-3) * s[a], m.m0, C(3) * m.m1[a]));
+        const int ea[6] = {0, 1, 2, 0, 0, 1}, eb[6] = {0, 1, 2, 1, 2, 2};
+        const C rc = rho * coef;
+#pragma unroll
+        for (int e = 0; e < 6; ++e) {
+            const int a = ea[e], b = eb[e];
+            C t = C(1.5) * M2[a][b];
+            if (a == b) t = fmad(C(-0.5), m.m0, t);
+            G[e] = fmad(rc, t, G[e]);
         }
     }
-    const C s[3] = {sx, sy, sz};
-    C Aa[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) Aa[a] = S1[a] - s[a] * S2;
-    if constexpr (ORDER == 3) {
-        Aa[0] -= C(3) * fmad(k.k[0], S3[0], fmad(k.k[3], S3[1], k.k[4] * S3[2]));
-        Aa[1] -= C(3) * fmad(k.k[3], S3[0], fmad(k.k[1], S3[1], k.k[5] * S3[2]));
-        Aa[2] -= C(3) * fmad(k.k[4], S3[0], fmad(k.k[5], S3[1], k.k[2] * S3[2]));
-    }
+    A0 = bracket;
     Ax = rho * Aa[0];
     Ay = rho * Aa[1];
     Az = rho * Aa[2];
-    // G_ab = rho [1.5 T_ab - 0.5 d_ab T0 + 4.5 U_ab - 1.5 d_ab U0 - 3 S3_a s_b] (the U, S3 terms
-    // at order 3); only the last term is not symmetric, and enters as -1.5 (S3_a s_b + S3_b s_a)
-    const int ea[6] = {0, 1, 2, 0, 0, 1}, eb[6] = {0, 1, 2, 1, 2, 2};
-    const C rc = rho * coef;
-#pragma unroll
-    for (int e = 0; e < 6; ++e) {
-        const int a = ea[e], b = eb[e];
-        C t = C(1.5) * T[e];
-        if (a == b) t -= C(0.5) * T0;
-        if constexpr (ORDER == 3) {
-            t = fmad(C(4.5), U[e], t);
-            if (a == b) t -= C(1.5) * U0;
-            t -= C(1.5) * fmad(S3[a], s[b], S3[b] * s[a]);
-        }
-        G[e] = fmad(rc, t, G[e]);
-    }
 }
 
 constexpr int kGradPartials = 7;  // symmetric G (6) and d tau, per work-group
@@ -582,8 +651,9 @@ __device__ inline void adjoint_cell(const S *__restrict__ state, const typename 
         const C w = k.omega;
         const C a = FORCED ? w - C(1) : w;
         // first pass over the directions: the transposed equilibrium Jacobian (and G)
+        const NuMoments<C> nm = nu_moments<LAT>(k, mup, mum, keep);
         C A0, Ax, Ay, Az;
-        equilibrium_vjp<LAT, ORDER, C>(k, rho, sx, sy, sz, mup, mum, keep, A0, Ax, Ay, Az, a, G);
+        moment_vjp<ORDER, C>(k, nm, rho, sx, sy, sz, A0, Ax, Ay, Az, a, G);
         C base = a * (A0 - (Ax * sx + Ay * sy + Az * sz) * inv);
         C ax = a * Ax * inv, ay = a * Ay * inv, az = a * Az * inv;
         C tx = C(0), ty = C(0), tz = C(0);
@@ -592,7 +662,7 @@ __device__ inline void adjoint_cell(const S *__restrict__ state, const typename 
             ty = (jy + k.force[1]) * inv;
             tz = (jz + k.force[2]) * inv;
             C B0, Bx, By, Bz;
-            equilibrium_vjp<LAT, ORDER, C>(k, rho, tx, ty, tz, mup, mum, keep, B0, Bx, By, Bz, C(1), G);
+            moment_vjp<ORDER, C>(k, nm, rho, tx, ty, tz, B0, Bx, By, Bz, C(1), G);
             base += B0 - (Bx * tx + By * ty + Bz * tz) * inv;
             ax += Bx * inv;
             ay += By * inv;
