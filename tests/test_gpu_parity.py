@@ -205,9 +205,13 @@ def test_row_spanning_tiles_match_oracle(lattice, storage, shape, steps):
     check(wl, storage, steps)
 
 
-def test_checkpoint_restore_is_exact():
-    wl = W.config2(lattice="D3Q27", shape=(24, 20, 18))
-    p = lbm.make_params(wl.lattice, "f32", wl.shape, wl.tensor, wl.tensor_kind, wl.tau)
+@pytest.mark.parametrize("lattice,storage,shape", [("D3Q27", "f32", (24, 20, 18)),   # one block per z-plane
+                                                   ("D3Q19", "f64", (300, 7, 3)),    # one row per block
+                                                   ("D3Q19", "f16", (96, 48, 3))])   # three blocks of 16 rows
+def test_checkpoint_restore_is_exact(lattice, storage, shape):
+    """Export to the canonical [q][N] order and import back through the blocked layout."""
+    wl = W.config2(lattice=lattice, shape=shape)
+    p = lbm.make_params(wl.lattice, storage, wl.shape, wl.tensor, wl.tensor_kind, wl.tau)
     a = lbm.Simulation(p, wl.rho, wl.s)
     a.step(13)
     snap = a.get_populations()
