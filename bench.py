@@ -27,8 +27,15 @@ stream-and-collide pass over the whole grid. Prints ONE JSON line:
                500 steps: the autotuned schedule's MLUPS and fraction of the 8 TB/s peak, beside
                fixed step-per-launch and persistent schedules
 
-Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-variants] [--no-adjoint] [--no-batched] [--batched-steps N]
-                       [--no-porous] [--porous-n N]
+  d2q9_64_shear_wave  the D2Q9 64^2 FP64 shear wave (1000 steps): the oracle's wall time, with the
+               GPU's time for the same steps as context
+
+The headline is the median of --runs timed runs of exactly --steps steps (after --warmup
+steps); every storage variant is timed over at least 200 steps after at least 50 warm-up steps.
+
+Usage: python bench.py [--steps K] [--warmup W] [--runs R] [--gpus 1] [--no-cpu-baseline] [--no-variants]
+                       [--no-adjoint] [--no-batched] [--batched-steps N] [--no-porous] [--porous-n N]
+                       [--leg LEG]   (one timed leg alone, for profilers; see LEGS)
 """
 import argparse
 import hashlib
@@ -36,6 +43,10 @@ import json
 import os
 import sys
 import time
+
+# the oracle's OpenMP runtime reads these when it starts: all host threads, pinned close
+os.environ.setdefault("OMP_PROC_BIND", "close")
+os.environ.setdefault("OMP_PLACES", "cores")
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -63,8 +74,78 @@ def parse():
     ap.add_argument("--batched-stepwise-only", action="store_true",
                     help="batched block: time the step-per-launch schedule only (no autotune, no cooperative launch)")
     ap.add_argument("--batched-steps", type=int, default=0, help="steps of the batched block (0: the workload's 500)")
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--runs", type=int, default=5, help="timed runs of --steps steps each; the median is reported")
+    ap.add_argument("--leg", choices=sorted(LEGS), default=None,
+                    help="run one timed leg alone (for profilers) and print its figures instead of the bench line")
     return ap.parse_args()
+
+
+# One timed leg each, for running under a profiler: the kernel named in the leg's record is
+# launched `--steps` times after `--warmup` steps on that leg's workload.
+LEGS = {
+    "step-f32": ("D3Q19 256^3 FP32 step (the headline kernel)", "step", "f32"),
+    "step-f16": ("D3Q19 256^3 FP16-shifted step", "step", "f16"),
+    "step-bf16": ("D3Q19 256^3 BF16-shifted step", "step", "bf16"),
+    "step-f64": ("D3Q19 256^3 FP64 step", "step", "f64"),
+    "porous-f32": ("D3Q27 porous medium 512^3, FP32 (links step with body force)", "porous", "f32"),
+    "porous-f16": ("D3Q27 porous medium 512^3, FP16-shifted (links step with body force)", "porous", "f16"),
+    "adjoint-d3q19": ("gradient workload D3Q19 128^3, FP32: lbm_grad over --steps steps", "adjoint", "f32"),
+    "batched": ("512 batched D3Q19 domains, FP32, step per launch", "batched", "f32"),
+}
+
+
+def run_leg(args):
+    """One leg alone: prints {leg, what, us_per_step, ...} as one JSON line."""
+    import numpy as np
+    import torch
+
+    import paper_2605_27004_amd as lbm
+    import workloads as W
+
+    torch.cuda.init()
+    what, kind, storage = LEGS[args.leg]
+    rec = {"leg": args.leg, "what": what, "steps": args.steps, "warmup": args.warmup}
+    if kind == "step":
+        wl = W.config2(n=args.n)
+        p = lbm.make_params(wl.lattice, storage, wl.shape, wl.tensor, wl.tensor_kind, wl.tau)
+        sim = lbm.Simulation(p, wl.rho, wl.s)
+        t = timed_steps(sim, args.steps, args.warmup, torch)
+        rec["us_per_step"] = round(t / args.steps * 1e6, 2)
+    elif kind == "porous":
+        wl3 = W.config3(n=args.porous_n)
+        mask = torch.as_tensor(wl3.meta["mask"]).cuda()
+        p3 = lbm.make_params("D3Q27", storage, wl3.shape, wl3.tensor, "theta", wl3.tau, force=wl3.meta["force"],
+                             masked=True)
+        sim = lbm.Simulation(p3, wl3.rho, wl3.s, mask=mask)
+        t = timed_steps(sim, args.steps, args.warmup, torch)
+        rec["us_per_step"] = round(t / args.steps * 1e6, 2)
+        rec["fluid_cells"] = int((wl3.meta["mask"] == 0).sum())
+    elif kind == "adjoint":
+        wl4 = W.config4("D3Q19")
+        gray = torch.as_tensor(wl4.meta["gray"].astype(np.float32), device="cuda")
+        p4 = lbm.make_params("D3Q19", storage, wl4.shape, wl4.tensor, "theta", wl4.tau, force=wl4.meta["force"],
+                             gray=True)
+        sim = lbm.Simulation(p4, wl4.rho, wl4.s, mask=gray)
+        sim.grad("flux", args.warmup, 10, wl4.meta["outlet_plane"], want_dmask=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.grad("flux", args.steps, 10, wl4.meta["outlet_plane"], want_dmask=True)
+        torch.cuda.synchronize()
+        rec["us_per_step"] = round((time.perf_counter() - t0) / args.steps * 1e6, 2)
+    else:
+        wl5 = W.config5()
+        bt = lbm.Batch(wl5.lattice, storage, wl5.domains)
+        bt.step(args.warmup)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(bt.stream)
+        bt.step(args.steps)
+        e1.record(bt.stream)
+        torch.cuda.synchronize()
+        rec["us_per_step"] = round(e0.elapsed_time(e1) * 1e3 / args.steps, 2)
+        bt.close()
+    print(json.dumps(rec), flush=True)
 
 
 def kernel_sha():
@@ -89,17 +170,28 @@ def traffic_per_launch():
     return int(kv["bytes_per_launch"])
 
 
-def timed_steps(sim, steps, warmup, torch):
+def timed_steps(sim, steps, warmup, torch, runs=1):
+    """Seconds for `steps` steps after `warmup` untimed ones, timed with HIP events on the stream
+    the kernels run on. With runs > 1: (median over `runs` timed runs back to back, all runs)."""
     sim.step(warmup)
     torch.cuda.synchronize()
     stream = sim.stream
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    sim.step(steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    return e0.elapsed_time(e1) / 1e3  # seconds
+    times = []
+    for _ in range(runs):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sim.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) / 1e3)
+    med = sorted(times)[len(times) // 2]
+    return (med, times) if runs > 1 else med
+
+
+# Every storage variant is timed over at least this much work, whatever --steps / --warmup say:
+# on a freshly created context the first steps run slower while clocks ramp up.
+VARIANT_WARMUP, VARIANT_STEPS = 50, 200
 
 
 def field_errors(a, b, u0):
@@ -116,6 +208,9 @@ def main():
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: the library runs on "
               "one GPU (the multi-GPU slab decomposition is described, not implemented).", file=sys.stderr)
         sys.exit(2)
+    if args.leg:
+        run_leg(args)
+        return
 
     import numpy as np
     import torch
@@ -132,35 +227,15 @@ def main():
         p = lbm.make_params(wl.lattice, storage, wl.shape, wl.tensor, wl.tensor_kind, wl.tau, order)
         return lbm.Simulation(p, wl.rho, wl.s)
 
-    # ---- headline: FP32 storage ----
-    sim = make("f32")
-    secs = timed_steps(sim, args.steps, args.warmup, torch)
-    mlups = cells * args.steps / secs / 1e6
-    kernel_s = secs / args.steps
-    alg_bytes = 2 * q * 4 * cells
-    achieved = alg_bytes / kernel_s / 1e9
-    _, _, tot = sim.moments(fields=False)
-    # data-movement floor: the same loads and stores without the collision
-    sim.stream_floor(args.warmup)
-    torch.cuda.synchronize()
-    f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    f0.record(sim.stream)
-    sim.stream_floor(args.steps)
-    f1.record(sim.stream)
-    torch.cuda.synchronize()
-    floor_s = f0.elapsed_time(f1) / 1e3 / args.steps
-    del sim
-    torch.cuda.empty_cache()
-
-    # ---- plain copy kernel over the same bytes (practical ceiling) ----
+    # ---- plain copy kernel over the same bytes (practical ceiling; also brings the clocks up) ----
     nbytes = q * 4 * cells
     src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
     stream = torch.cuda.current_stream()
-    for _ in range(3):
+    for _ in range(20):
         lbm.lbm_stream_copy(dst, src, nbytes, stream.cuda_stream)
     torch.cuda.synchronize()
-    reps = 20
+    reps = 50
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(reps):
@@ -169,6 +244,31 @@ def main():
     torch.cuda.synchronize()
     copy_gbps = 2 * nbytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
     del src, dst
+    torch.cuda.empty_cache()
+
+    # ---- headline: FP32 storage, median of --runs timed runs of exactly --steps steps ----
+    sim = make("f32")
+    runs = max(1, args.runs)
+    if runs > 1:
+        secs, run_secs = timed_steps(sim, args.steps, args.warmup, torch, runs=runs)
+    else:
+        secs, run_secs = timed_steps(sim, args.steps, args.warmup, torch), None
+    mlups = cells * args.steps / secs / 1e6
+    kernel_s = secs / args.steps
+    alg_bytes = 2 * q * 4 * cells
+    achieved = alg_bytes / kernel_s / 1e9
+    _, _, tot = sim.moments(fields=False)
+    # data-movement floor: the same loads and stores without the collision
+    nfl = max(args.steps, VARIANT_STEPS)
+    sim.stream_floor(max(args.warmup, VARIANT_WARMUP))
+    torch.cuda.synchronize()
+    f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    f0.record(sim.stream)
+    sim.stream_floor(nfl)
+    f1.record(sim.stream)
+    torch.cuda.synchronize()
+    floor_s = f0.elapsed_time(f1) / 1e3 / nfl
+    del sim
     torch.cuda.empty_cache()
 
     line = {
@@ -194,6 +294,8 @@ def main():
                      "copy_kernel_GBps": round(copy_gbps, 1), "frac_of_copy": round(achieved / copy_gbps, 4),
                      "stream_floor_us": round(floor_s * 1e6, 1), "frac_of_stream_floor": round(floor_s / kernel_s, 4)},
         "mass_total": tot[0],
+        "timing": {"runs": runs, "statistic": "median",
+                   "run_ms_per_step": None if run_secs is None else [round(t / args.steps * 1e3, 5) for t in run_secs]},
     }
 
     # ---- storage variants: speed and error against the FP64 path at full size ----
@@ -208,14 +310,16 @@ def main():
 
         ref = run_fields("f64", wl.steps)
         variants = {}
+        n_ = max(args.steps, VARIANT_STEPS)
+        w_ = max(args.warmup, VARIANT_WARMUP)
         for storage, sz in (("f16", 2), ("bf16", 2), ("f64", 8)):
             s_ = make(storage)
-            t_ = timed_steps(s_, min(args.steps, 500), args.warmup, torch)
-            n_ = min(args.steps, 500)
+            t_ = timed_steps(s_, n_, w_, torch)
             del s_
             torch.cuda.empty_cache()
             v = {"MLUPS": round(cells * n_ / t_ / 1e6, 1),
-                 "frac": round(2 * q * sz * cells / (t_ / n_) / 1e9 / PEAK_GBPS, 4)}
+                 "frac": round(2 * q * sz * cells / (t_ / n_) / 1e9 / PEAK_GBPS, 4),
+                 "us_per_step": round(t_ / n_ * 1e6, 2), "timed_steps": n_, "warmup_steps": w_}
             if storage != "f64":
                 got = run_fields(storage, wl.steps)
                 v["err_vs_f64_after_%d_steps" % wl.steps] = field_errors(got, ref, wl.u0)
@@ -226,11 +330,11 @@ def main():
         variants["f32_shifted"] = {"err_vs_f64_after_%d_steps" % wl.steps: field_errors(got, ref, wl.u0)}
         # cost of the third-order term: the same FP32 step with the second-order equilibrium
         s_ = make("f32", order=2)
-        n_ = min(args.steps, 500)
-        t_ = timed_steps(s_, n_, args.warmup, torch)
+        t_ = timed_steps(s_, n_, w_, torch)
         del s_
         variants["f32_order2"] = {"MLUPS": round(cells * n_ / t_ / 1e6, 1),
-                                  "frac": round(2 * q * 4 * cells / (t_ / n_) / 1e9 / PEAK_GBPS, 4)}
+                                  "frac": round(2 * q * 4 * cells / (t_ / n_) / 1e9 / PEAK_GBPS, 4),
+                                  "us_per_step": round(t_ / n_ * 1e6, 2), "timed_steps": n_, "warmup_steps": w_}
         del got, ref
         torch.cuda.empty_cache()
         line["variants"] = variants
@@ -274,11 +378,11 @@ def main():
                                  masked=True)
             s3 = lbm.Simulation(p3, wl3.rho, wl3.s, mask=mask)
             n3 = 50
-            t3 = timed_steps(s3, n3, 5, torch) / n3
+            t3 = timed_steps(s3, n3, 10, torch) / n3
             useful = fluid * 2 * 27 * sz + wl3.cells * 4
             rec = {"MLUPS": round(wl3.cells / t3 / 1e6, 1), "fluid_MLUPS": round(fluid / t3 / 1e6, 1),
                    "frac": round(useful / t3 / 1e9 / PEAK_GBPS, 4), "ms_per_step": round(t3 * 1e3, 4)}
-            s3.step(wl3.steps - n3 - 5)
+            s3.step(wl3.steps - n3 - 10)
             rho3, sv3, _ = s3.moments()
             torch.cuda.synchronize()
             if ref3 is None:
@@ -364,7 +468,27 @@ def main():
         line["cpu_baseline"] = {"value": round(cells * args.cpu_steps / dt / 1e6, 3), "unit": "MLUPS",
                                 "cores": oracle.num_threads(), "kind": "oracle",
                                 "sample": f"FP64 oracle, {args.cpu_steps} steps of the full {args.n}^3 D3Q19 "
-                                          f"workload (init excluded), {dt:.1f} s on {cpu_name}"}
+                                          f"workload (init excluded), {dt:.1f} s on {cpu_name}, "
+                                          f"OMP_PROC_BIND={os.environ.get('OMP_PROC_BIND')}"}
+        # the D2Q9 64^2 shear wave (FP64, 1000 steps): its metric is the oracle's wall time, with the
+        # GPU's time for the same steps as context (the grid is cache-resident, not an HBM test)
+        wl1 = W.config1()
+        ainv1 = oracle.tensor_to_ainv(wl1.tensor, wl1.tensor_kind, 2)
+        f1 = oracle.init(wl1.lattice, wl1.shape, ainv1, wl1.rho, wl1.s)
+        t0 = time.perf_counter()
+        oracle.steps(wl1.lattice, wl1.shape, ainv1, wl1.tau, f1, wl1.steps)
+        dt1 = time.perf_counter() - t0
+        p1 = lbm.make_params(wl1.lattice, "f64", wl1.shape, wl1.tensor, wl1.tensor_kind, wl1.tau)
+        g1 = lbm.Simulation(p1, wl1.rho, wl1.s)
+        g1.step(20)
+        torch.cuda.synchronize()
+        g1.close()
+        g1 = lbm.Simulation(p1, wl1.rho, wl1.s)
+        tg1 = timed_steps(g1, wl1.steps, 0, torch)
+        g1.close()
+        line["d2q9_64_shear_wave"] = {"workload": "D2Q9 64^2 periodic shear wave, FP64, tau=0.8, 1000 steps",
+                                      "oracle_wall_s": round(dt1, 4), "oracle_cores": oracle.num_threads(),
+                                      "gpu_s": round(tg1, 5), "gpu_MLUPS": round(wl1.cells * wl1.steps / tg1 / 1e6, 1)}
     print(json.dumps(line), flush=True)
 
 

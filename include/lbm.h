@@ -91,7 +91,8 @@ typedef struct lbm_params {
     int32_t flags;       /* LBM_FLAG_* bits; 0 for a fully periodic fluid grid              */
     int64_t nx, ny, nz;  /* grid extents, each >= 1; nz == 1 for D2Q9; periodic on all faces */
     double tensor[9];    /* 3 x 3 row-major; leading d x d block used; must be symmetric
-                            (|T - T^T| <= 1e-12 |T|) and positive definite                 */
+                            (|T - T^T| <= 1e-12 |T|) and positive definite. It enters as
+                            (T + T^T) / 2, so derivatives split evenly over T_ab and T_ba. */
     double tau;          /* BGK relaxation time of eq:LBE_BGK, > 1/2                       */
     double rho0;         /* reference density of the shift sigma_i, > 0 (usually 1)        */
     double force[3];     /* body force F per cell (lattice units, momentum per step), added by
@@ -139,6 +140,12 @@ int lbm_prepare(const lbm_params *p, lbm_derived *out);
 
 /* Bytes of one population array: q * nx * ny * nz * sizeof(storage). -1 if p is invalid. */
 int64_t lbm_pop_bytes(const lbm_params *p);
+
+/* Rows per block of the private population layout (host only): each z-plane is stored as
+ * ny / rows blocks of `rows` consecutive y-rows, a block holding its q direction planes one
+ * after another; rows is the largest divisor of ny with rows * nx * sizeof(storage) <= 8 KiB
+ * (32 KiB for FP64), at least 1. For tests and tools; -1 if p is invalid. */
+int64_t lbm_rows_per_block(const lbm_params *p);
 
 /* Bytes of device scratch lbm_init needs (reduction partials, plus 4 bytes per cell of link
  * words or gray fractions when LBM_FLAG_MASK or LBM_FLAG_GRAY is set). -1 if p is invalid. */
@@ -190,7 +197,10 @@ int64_t lbm_time(const lbm_ctx *ctx);
 
 /* Step-kernel launch options: work-group shape block_x * block_y cells (block_x a multiple of
  * 64, block_x * block_y <= 256; the default spans whole x rows up to 256 cells) and flags. */
-#define LBM_LAUNCH_XCD_SLABS 1 /* hand each of the 8 XCDs one contiguous slab of tiles */
+#define LBM_LAUNCH_XCD_SLABS 1    /* hand each of the 8 XCDs one contiguous slab of tiles */
+#define LBM_LAUNCH_SHIFTED_PULL 2 /* pull every population with its own shifted load. By default, when
+                                     nx is a multiple of 64 and of block_x, x-shifted pulls load the
+                                     lane's own x and move the values one lane across the wave. */
 
 /* Override the step kernel's launch. Results do not depend on it: every cell is computed by
  * the same arithmetic whatever work-group computes it. */
@@ -227,7 +237,10 @@ int64_t lbm_grad_workspace_bytes(const lbm_ctx *ctx, const lbm_grad_spec *spec);
 /*   workspace: device buffer of lbm_grad_workspace_bytes, 256-byte aligned.
  *   objective: host out, J.
  *   dtensor:   host out [9] (may be NULL): dJ/dT_ab for the tensor as given, one value per
- *              independent entry (T_ab and T_ba are one entry), written symmetrically.
+ *              independent entry (T_ab and T_ba are one entry), written symmetrically: off the
+ *              diagonal it is the derivative with respect to v when T_ab = T_ba = v, twice the
+ *              derivative with respect to either element alone (the tensor enters as
+ *              (T + T^T) / 2).
  *   dtau:      host out (may be NULL): dJ/dtau.
  *   dmask:     device out FP64 [N] (may be NULL): dJ/dm per cell for the gray fraction m of
  *              the partial bounce-back blend. With a gray field it is the derivative at the
@@ -236,6 +249,12 @@ int64_t lbm_grad_workspace_bytes(const lbm_ctx *ctx, const lbm_grad_spec *spec);
  * Synchronises the stream before returning. */
 int lbm_grad(lbm_ctx *ctx, const lbm_grad_spec *spec, void *workspace, double *objective, double *dtensor,
              double *dtau, double *dmask);
+
+/* The objective J of lbm_grad (objective 0: mass flux through the plane x = outlet_plane;
+ * 1: kinetic energy) on the current state, summed in FP64 on the device in a fixed order, with
+ * no adjoint work: the same value lbm_grad returns for a final state. value: host out.
+ * Synchronises the stream. */
+int lbm_objective(lbm_ctx *ctx, int32_t objective, int64_t outlet_plane, double *value);
 
 /* Measurement aid: nsteps passes of free streaming (every population moved along its velocity,
  * no collision) with exactly the step kernel's loads and stores, work-group shape and launch.

@@ -12,6 +12,8 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "lib", "liblbm.so")
 
@@ -31,6 +33,7 @@ LBM_F64, LBM_F32, LBM_F16, LBM_BF16 = 0, 1, 2, 3
 LBM_TENSOR_THETA, LBM_TENSOR_A, LBM_TENSOR_ATILDE = 0, 1, 2
 LBM_SHIFT_REST, LBM_SHIFT_WEIGHT = 0, 1
 LBM_LAUNCH_XCD_SLABS = 1
+LBM_LAUNCH_SHIFTED_PULL = 2
 LBM_FLAG_MASK = 1
 LBM_FLAG_GRAY = 2
 
@@ -115,6 +118,7 @@ def _bind(path: str):
         "lbm_lattice_info": (ctypes.c_int, [i32, ip32, ip32, ip32, dp, ip32]),
         "lbm_prepare": (ctypes.c_int, [ctypes.POINTER(lbm_params), ctypes.POINTER(lbm_derived)]),
         "lbm_pop_bytes": (i64, [ctypes.POINTER(lbm_params)]),
+        "lbm_rows_per_block": (i64, [ctypes.POINTER(lbm_params)]),
         "lbm_scratch_bytes": (i64, [ctypes.POINTER(lbm_params)]),
         "lbm_init": (ctypes.c_int, [ctypes.POINTER(vp), ctypes.POINTER(lbm_params), vp, vp, vp, vp, vp, vp, vp]),
         "lbm_step": (ctypes.c_int, [vp, i64]),
@@ -127,6 +131,7 @@ def _bind(path: str):
         "lbm_set_launch": (ctypes.c_int, [vp, i32, i32, i32]),
         "lbm_grad_workspace_bytes": (i64, [vp, ctypes.POINTER(lbm_grad_spec)]),
         "lbm_grad": (ctypes.c_int, [vp, ctypes.POINTER(lbm_grad_spec), vp, dp, dp, dp, vp]),
+        "lbm_objective": (ctypes.c_int, [vp, i32, i64, dp]),
         "lbm_destroy": (None, [vp]),
         "lbm_last_error": (ctypes.c_char_p, []),
         "lbm_stream_copy": (ctypes.c_int, [vp, vp, i64, vp]),
@@ -235,6 +240,13 @@ def lbm_pop_bytes(p: lbm_params) -> int:
     return n
 
 
+def lbm_rows_per_block(p: lbm_params) -> int:
+    n = _lib.lbm_rows_per_block(ctypes.byref(p))
+    if n < 0:
+        _check(_lib.lbm_prepare(ctypes.byref(p), None))
+    return int(n)
+
+
 def lbm_scratch_bytes(p: lbm_params) -> int:
     n = _lib.lbm_scratch_bytes(ctypes.byref(p))
     if n < 0:
@@ -309,6 +321,13 @@ def lbm_grad(ctx: int, spec: lbm_grad_spec, workspace, dmask=None):
     _check(_lib.lbm_grad(ctx, ctypes.byref(spec), _ptr(workspace), ctypes.byref(obj), dt, ctypes.byref(du),
                          _ptr(dmask)))
     return obj.value, [list(dt[3 * a: 3 * a + 3]) for a in range(3)], du.value
+
+
+def lbm_objective(ctx: int, objective="kinetic_energy", outlet_plane: int = 0) -> float:
+    val = ctypes.c_double()
+    kind = OBJECTIVES[objective] if isinstance(objective, str) else int(objective)
+    _check(_lib.lbm_objective(ctx, kind, int(outlet_plane), ctypes.byref(val)))
+    return val.value
 
 
 def lbm_destroy(ctx: int) -> None:
@@ -453,7 +472,7 @@ class Simulation:
     f^eq(rho, s). Work goes to ``stream`` (a torch.cuda.Stream) or torch's current stream.
     """
 
-    def __init__(self, params: lbm_params, rho, s, device="cuda", stream=None, mask=None):
+    def __init__(self, params: lbm_params, rho, s, device="cuda", stream=None, mask=None, buffers=None):
         import torch
 
         self.torch = torch
@@ -461,13 +480,15 @@ class Simulation:
         self.derived = lbm_prepare(params)
         self.q, self.d = self.derived.q, self.derived.d
         self.n = params.nx * params.ny * params.nz
-        self.device = torch.device(device)
+        self.device = _device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        nbytes = lbm_pop_bytes(params)
-        # 256-byte aligned by the caching allocator
-        self.pop_a = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        self.pop_b = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        self.scratch = torch.empty(lbm_scratch_bytes(params), dtype=torch.uint8, device=self.device)
+        # buffers: an optional dict kept by the caller; its device buffers are reused when large
+        # enough (256-byte aligned by the caching allocator either way)
+        bufs = buffers if buffers is not None else {}
+        self.pop_a = _buffer(bufs, "pop_a", lbm_pop_bytes(params), self.device)
+        self.pop_b = _buffer(bufs, "pop_b", lbm_pop_bytes(params), self.device)
+        self.scratch = _buffer(bufs, "scratch", lbm_scratch_bytes(params), self.device)
+        self._bufs = bufs
         rho_t = torch.as_tensor(rho, dtype=torch.float64).reshape(self.n).to(self.device)
         s_t = torch.as_tensor(s, dtype=torch.float64).reshape(self.d, self.n).to(self.device).contiguous()
         mask_t = None
@@ -531,49 +552,146 @@ class Simulation:
 
     def grad(self, objective="kinetic_energy", nsteps=0, checkpoint_every=100, outlet_plane=0, want_dmask=True):
         """Advance nsteps and return (J, dJ/dtensor [3 x 3], dJ/dtau, dJ/dm [N] device tensor or None)
-        by the adjoint (see lbm_grad); the workspace is allocated with torch for this call."""
+        by the adjoint (see lbm_grad). The workspace comes from the buffers dict given at
+        construction (reused when large enough) or is allocated for this call."""
         torch = self.torch
         spec = make_grad_spec(objective, nsteps, checkpoint_every, outlet_plane)
-        ws = torch.empty(lbm_grad_workspace_bytes(self.ctx, spec), dtype=torch.uint8, device=self.device)
+        ws = _buffer(self._bufs, "workspace", lbm_grad_workspace_bytes(self.ctx, spec), self.device)
         dmask = torch.empty(self.n, dtype=torch.float64, device=self.device) if want_dmask else None
         j, dt, du = lbm_grad(self.ctx, spec, ws, dmask)
         return j, dt, du, dmask
 
+    def objective(self, objective="kinetic_energy", outlet_plane=0) -> float:
+        """J of the current state (see lbm_objective)."""
+        return lbm_objective(self.ctx, objective, outlet_plane)
+
+
+def _device(device):
+    """torch.device with its index resolved ("cuda" -> the current CUDA device)."""
+    import torch
+
+    d = torch.device(device)
+    if d.type == "cuda" and d.index is None:
+        d = torch.device("cuda", torch.cuda.current_device())
+    return d
+
+
+def _buffer(bufs: dict, key: str, nbytes: int, device):
+    """A uint8 device tensor of at least nbytes from bufs[key], replaced when too small."""
+    import torch
+
+    buf = bufs.get(key)
+    if buf is None or buf.numel() < nbytes or buf.device != device:
+        buf = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+        bufs[key] = buf
+    return buf
+
 
 class Objective:
-    """torch.autograd.Function factory: J(tensor, tau, gray) of a fixed workload, with the
-    gradients from one lbm_grad call (the forward computes them; backward scales them)."""
+    """J(tensor, tau, gray) of a fixed workload as a differentiable torch function.
 
-    @staticmethod
-    def function():
+    ``cfg`` holds lattice, storage, shape, rho [N], s [d][N] and optionally tensor_kind, order,
+    force, objective ("flux" or "kinetic_energy"), nsteps, checkpoint_every and outlet_plane.
+    ``obj(tensor, tau, gray=None)`` returns J (a float64 scalar tensor) after nsteps from
+    f^eq(rho, s) with the given tensor (d x d or 3 x 3), tau and optional gray field [N].
+
+    The adjoint runs only when grad mode is on and an input requires a gradient: then one
+    lbm_grad call gives J and every gradient, and backward scales them. Otherwise the call is
+    one forward pass (lbm_step) and lbm_objective. Device buffers (populations, scratch,
+    gradient workspace) and the initial fields live on the object and are reused across calls.
+
+    The tensor enters the update as (T + T^T) / 2, so the gradient of an off-diagonal element
+    is half of lbm_grad's symmetric-direction derivative.
+    """
+
+    def __init__(self, cfg: dict, device="cuda"):
         import torch
 
-        class _Fn(torch.autograd.Function):
-            @staticmethod
-            def forward(ctx, tensor, tau, gray, cfg):
-                p = make_params(cfg["lattice"], cfg["storage"], cfg["shape"], tensor.detach().cpu().numpy(),
-                                cfg.get("tensor_kind", "theta"), float(tau), cfg.get("order", 3),
-                                force=cfg.get("force"), gray=gray is not None)
-                sim = Simulation(p, cfg["rho"], cfg["s"], mask=None if gray is None else gray.detach())
-                j, dt, du, dm = sim.grad(cfg.get("objective", "kinetic_energy"), cfg["nsteps"],
-                                         cfg.get("checkpoint_every", 100), cfg.get("outlet_plane", 0),
-                                         want_dmask=gray is not None)
-                sim.close()
-                ctx.save_for_backward(torch.tensor(dt, dtype=tensor.dtype), torch.tensor(du, dtype=torch.float64),
-                                      dm if dm is not None else torch.zeros(0))
-                ctx.has_gray = gray is not None
-                ctx.gray_dtype = None if gray is None else gray.dtype
-                return torch.tensor(j, dtype=torch.float64)
+        self.cfg = dict(cfg)
+        self.device = _device(device)
+        self.d = 2 if self.cfg["lattice"] == "D2Q9" else 3
+        n = int(np.prod(self.cfg["shape"]))
+        self._rho = torch.as_tensor(self.cfg["rho"], dtype=torch.float64).reshape(n).to(self.device)
+        self._s = torch.as_tensor(self.cfg["s"], dtype=torch.float64).reshape(self.d, n).to(self.device).contiguous()
+        self._bufs = {}
+        self.adjoint_calls = 0
+        self.forward_calls = 0
 
-            @staticmethod
-            def backward(ctx, gout):
-                dt, du, dm = ctx.saved_tensors
-                gt = (gout.cpu() * dt).to(dt.dtype)
-                gu = gout.cpu() * du
-                gg = (gout.to(dm.device) * dm).to(ctx.gray_dtype) if ctx.has_gray else None
-                return gt, gu, gg, None
+    def _simulation(self, tensor, tau, gray):
+        cfg = self.cfg
+        p = make_params(cfg["lattice"], cfg["storage"], cfg["shape"], tensor.detach().cpu().double().numpy(),
+                        cfg.get("tensor_kind", "theta"), float(tau), cfg.get("order", 3), force=cfg.get("force"),
+                        gray=gray is not None)
+        return Simulation(p, self._rho, self._s, device=self.device, mask=None if gray is None else gray.detach(),
+                          buffers=self._bufs)
 
-        return _Fn
+    def value(self, tensor, tau, gray=None) -> float:
+        """J alone: one forward pass, no adjoint."""
+        cfg = self.cfg
+        sim = self._simulation(tensor, tau, gray)
+        sim.step(cfg["nsteps"])
+        j = sim.objective(cfg.get("objective", "kinetic_energy"), cfg.get("outlet_plane", 0))
+        sim.close()
+        self.forward_calls += 1
+        return j
+
+    def gradients(self, tensor, tau, gray=None):
+        """(J, dJ/dtensor per element [3 x 3] numpy, dJ/dtau, dJ/dm [N] device tensor or None)."""
+        cfg = self.cfg
+        sim = self._simulation(tensor, tau, gray)
+        j, dt, du, dm = sim.grad(cfg.get("objective", "kinetic_energy"), cfg["nsteps"], cfg.get("checkpoint_every", 100),
+                                 cfg.get("outlet_plane", 0), want_dmask=gray is not None)
+        sim.close()
+        self.adjoint_calls += 1
+        dt = np.array(dt)
+        off = ~np.eye(3, dtype=bool)
+        dt[off] *= 0.5  # lbm_grad reports the derivative along E_ab + E_ba off the diagonal
+        return j, dt, du, dm
+
+    def __call__(self, tensor, tau, gray=None):
+        import torch
+
+        tau_t = torch.as_tensor(tau, dtype=torch.float64)
+        track = torch.is_grad_enabled() and any(
+            isinstance(t, torch.Tensor) and t.requires_grad for t in (tensor, tau, gray))
+        if not track:
+            return torch.tensor(self.value(tensor, float(tau_t), gray), dtype=torch.float64)
+        return _objective_fn().apply(tensor, tau if isinstance(tau, torch.Tensor) else tau_t, gray, self)
+
+
+_OBJECTIVE_FN = None
+
+
+def _objective_fn():
+    """The torch.autograd.Function behind Objective (built on first use)."""
+    global _OBJECTIVE_FN
+    if _OBJECTIVE_FN is not None:
+        return _OBJECTIVE_FN
+    import torch
+
+    class _Fn(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, tensor, tau, gray, obj):
+            j, dt, du, dm = obj.gradients(tensor, float(tau), gray)
+            d = tensor.shape[-1]
+            ctx.save_for_backward(torch.as_tensor(dt[:d, :d], dtype=tensor.dtype, device=tensor.device),
+                                  torch.as_tensor(du, dtype=tau.dtype, device=tau.device),
+                                  dm if dm is not None else torch.zeros(0))
+            ctx.gray_dtype = None if gray is None else gray.dtype
+            return torch.tensor(j, dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, gout):
+            dt, du, dm = ctx.saved_tensors
+            gt = (gout.to(dt.device, torch.float64) * dt.double()).to(dt.dtype)
+            gu = (gout.to(du.device, torch.float64) * du.double()).to(du.dtype)
+            gg = None
+            if ctx.gray_dtype is not None:
+                gg = (gout.to(dm.device, torch.float64) * dm).to(ctx.gray_dtype)
+            return gt, gu, gg, None
+
+    _OBJECTIVE_FN = _Fn
+    return _Fn
 
 
 class Batch:

@@ -204,6 +204,10 @@ int prepare(const lbm_params *p, Prepared &out)
         for (int b = a + 1; b < d; ++b)
             if (std::fabs(t[a * d + b] - t[b * d + a]) > 1e-12 * tmax)
                 return fail(LBM_ERR_NOT_SPD, "tensor is not symmetric (T[%d][%d] != T[%d][%d])", a, b, b, a);
+    // the tensor enters as its symmetric part (T + T^T) / 2 (equal to T within the check above),
+    // so the update, and every derivative of it, depends on T_ab and T_ba alike
+    for (int a = 0; a < d; ++a)
+        for (int b = a + 1; b < d; ++b) t[a * d + b] = t[b * d + a] = 0.5 * (t[a * d + b] + t[b * d + a]);
     double l[9], ainv[9];
     if (!cholesky(d, t, l)) return fail(LBM_ERR_NOT_SPD, "tensor is not positive definite");
     if (p->tensor_kind == LBM_TENSOR_THETA) {
@@ -297,23 +301,6 @@ template StepConsts<double> consts_for<double>(const lbm_params &, const Prepare
 
 using namespace lbm::host;
 
-struct lbm_ctx {
-    lbm_params p;
-    Prepared pr;
-    Grid grid;
-    StepConsts<double> k64;
-    StepConsts<float> k32;
-    void *pop[2];
-    int cur;
-    double *partials;
-    uint32_t *links;  // null without a solid mask
-    float *gray;      // null without a gray field
-    hipStream_t stream;
-    int64_t t;
-    int block_x, block_y;
-    int launch_flags;
-};
-
 extern "C" {
 
 int lbm_lattice_info(int32_t lattice, int32_t *q, int32_t *d, int32_t *c, double *w, int32_t *opp)
@@ -347,13 +334,21 @@ int64_t lbm_pop_bytes(const lbm_params *p)
     return (int64_t)pr.q * (int64_t)pr.n * pr.bytes;
 }
 
+int64_t lbm_rows_per_block(const lbm_params *p)
+{
+    Prepared pr;
+    if (prepare(p, pr)) return -1;
+    return grid_of(p->nx, p->ny, p->nz, pr.q, pr.bytes).rows;
+}
+
 int64_t lbm_scratch_bytes(const lbm_params *p)
 {
     Prepared pr;
     if (prepare(p, pr)) return -1;
     const Grid g = grid_of(p->nx, p->ny, p->nz, pr.q, pr.bytes);
-    // kPartials sums per reduction block, then kPartials totals, rounded up to 256 bytes
-    const int64_t bytes = 8 * (kPartials * (int64_t)moments_blocks(g) + kPartials);
+    // kPartials sums per work-group of the moments launch, then kPartials totals, rounded up
+    // to 256 bytes
+    const int64_t bytes = 8 * (kPartials * (int64_t)moments_groups(g) + kPartials);
     return links_bytes(*p, pr.n) + (bytes + 255) / 256 * 256;
 }
 
@@ -440,7 +435,7 @@ int lbm_step(lbm_ctx *c, int64_t nsteps)
 int lbm_moments(lbm_ctx *c, double *rho, double *s, double *totals)
 {
     if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
-    const uint32_t nb = moments_blocks(c->grid);
+    const uint32_t nb = moments_groups(c->grid);
     double *partials = c->partials;
     double *dtot = c->partials + kPartials * (size_t)nb;
     hipError_t e = launch_moments(c->p.lattice, c->p.storage, c->grid, c->k64, c->links, c->pop[c->cur], rho, s,
@@ -491,7 +486,8 @@ int64_t lbm_time(const lbm_ctx *c) { return c ? c->t : -1; }
 int lbm_set_launch(lbm_ctx *c, int32_t block_x, int32_t block_y, int32_t flags)
 {
     if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
-    if (flags & ~LBM_LAUNCH_XCD_SLABS) return fail(LBM_ERR_ARG, "unknown launch flags 0x%x", flags);
+    if (flags & ~(LBM_LAUNCH_XCD_SLABS | LBM_LAUNCH_SHIFTED_PULL))
+        return fail(LBM_ERR_ARG, "unknown launch flags 0x%x", flags);
     if (block_x < 64 || block_x % 64 != 0 || block_y < 1 || block_x * block_y > 256)
         return fail(LBM_ERR_ARG, "block shape %d x %d: need block_x a multiple of 64 and block_x*block_y <= 256",
                     block_x, block_y);
@@ -525,7 +521,7 @@ int grad_layout(const lbm_ctx *c, const lbm_grad_spec *spec, GradLayout &l)
     // half storage), and one z-plane of them must stay below 4 GiB as well
     if ((double)c->pr.q * (double)c->p.nx * (double)c->p.ny * lam_bytes >= 4294967296.0)
         return fail(LBM_ERR_SIZE, "one z-plane of the adjoint populations would hold 4 GiB or more");
-    const int64_t nb = moments_blocks(c->grid), na = adjoint_blocks(c->grid);
+    const int64_t nb = moments_groups(c->grid), na = adjoint_blocks(c->grid);
     l.seglen = std::min<int64_t>(spec->checkpoint_every, std::max<int64_t>(spec->nsteps, 1));
     l.nseg = (spec->nsteps + spec->checkpoint_every - 1) / spec->checkpoint_every;
     int64_t off = 0;
@@ -567,7 +563,7 @@ int lbm_grad(lbm_ctx *c, const lbm_grad_spec *spec, void *workspace, double *obj
     char *ws = (char *)workspace;
     const int64_t popb = (int64_t)c->pr.q * c->grid.n * c->pr.bytes;
     const int64_t pstride = align256(popb);
-    const uint32_t nb = moments_blocks(c->grid), na = adjoint_blocks(c->grid);
+    const uint32_t nb = moments_groups(c->grid), na = adjoint_blocks(c->grid);
     hipStream_t st = c->stream;
     hipError_t e = hipSuccess;
     auto ckpt = [&](int64_t s) { return (void *)(ws + l.ckpt + s * pstride); };
@@ -637,7 +633,9 @@ int lbm_grad(lbm_ctx *c, const lbm_grad_spec *spec, void *workspace, double *obj
                     D[a * 3 + b] = -v;
                 }
             if (c->p.tensor_kind == LBM_TENSOR_ATILDE) {
-                const double *T = c->p.tensor;
+                double T[9];
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) T[a * 3 + b] = 0.5 * (c->p.tensor[a * 3 + b] + c->p.tensor[b * 3 + a]);
                 const double det = d == 2 ? T[0] * T[4] - T[1] * T[3]
                                           : T[0] * (T[4] * T[8] - T[5] * T[7]) - T[1] * (T[3] * T[8] - T[5] * T[6]) +
                                                 T[2] * (T[3] * T[7] - T[4] * T[6]);
@@ -656,6 +654,24 @@ int lbm_grad(lbm_ctx *c, const lbm_grad_spec *spec, void *workspace, double *obj
             }
     }
     return LBM_OK;
+}
+
+int lbm_objective(lbm_ctx *c, int32_t objective, int64_t outlet_plane, double *value)
+{
+    if (!c || !value) return fail(LBM_ERR_ARG, "NULL argument");
+    if (objective != 0 && objective != 1) return fail(LBM_ERR_ARG, "objective must be 0 or 1");
+    if (objective == 0 && (outlet_plane < 0 || outlet_plane >= c->p.nx))
+        return fail(LBM_ERR_ARG, "outlet_plane %lld outside 0..%lld", (long long)outlet_plane,
+                    (long long)(c->p.nx - 1));
+    // the moments partials hold one double per seed work-group, the totals slot the sum
+    double *jpart = c->partials;
+    double *sum = c->partials + kPartials * (size_t)moments_groups(c->grid);
+    hipError_t e = launch_seed(c->p.lattice, c->p.storage, c->grid, c->k64, c->k32, c->pop[c->cur], nullptr, jpart,
+                               objective, (int)outlet_plane, c->links, c->stream);
+    if (e == hipSuccess) e = launch_sum(jpart, moments_groups(c->grid), 1, sum, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(value, sum, sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return e == hipSuccess ? LBM_OK : fail_hip(e, "objective evaluation");
 }
 
 void lbm_destroy(lbm_ctx *c) { delete c; }

@@ -229,9 +229,42 @@ template <typename S> __device__ inline void st_stream(S *p, uint32_t idx, S v)
     __builtin_nontemporal_store(v, reinterpret_cast<S *>(reinterpret_cast<char *>(p) + (uint32_t)(idx * (uint32_t)sizeof(S))));
 }
 
+// Non-temporal load of one element (16-bit types go through their bit pattern).
+template <typename S> __device__ inline S ld_nt_at(const S *p, uint32_t idx)
+{
+    const char *a = reinterpret_cast<const char *>(p) + (uint32_t)(idx * (uint32_t)sizeof(S));
+    if constexpr (sizeof(S) == 2) {
+        return __builtin_bit_cast(S, __builtin_nontemporal_load(reinterpret_cast<const uint16_t *>(a)));
+    } else {
+        return __builtin_nontemporal_load(reinterpret_cast<const S *>(a));
+    }
+}
+
 template <typename S> __device__ inline S ld_pop(const S *base, const Grid &g, int i, const Ref &r)
 {
     return ld_at(pop_base(base, g, i, r), r.idx);
+}
+
+// ---- one-lane shifts across a 64-lane wave ----------------------------------------------
+//
+// DPP wave shifts: kFromLeft gives lane l the value of lane l - 1 (wave_shr:1) and kFromRight
+// the value of lane l + 1 (wave_shl:1); the lane with no source in the wave (0, resp. 63)
+// receives `edge`. They need all 64 lanes active.
+constexpr int kFromLeft = 0x138;
+constexpr int kFromRight = 0x130;
+
+template <int CTRL> __device__ inline float wave_shift(float edge, float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, edge),
+                                                                 __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL> __device__ inline double wave_shift(double edge, double v)
+{
+    const uint64_t e = __builtin_bit_cast(uint64_t, edge), w = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)e, (int)(uint32_t)w, CTRL, 0xF, 0xF, false);
+    const uint32_t hi =
+        (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(e >> 32), (int)(uint32_t)(w >> 32), CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 template <typename S> __device__ inline void st_pop(S *base, const Grid &g, int i, const Ref &r, S v)
 {
@@ -394,8 +427,11 @@ __device__ inline void close_moments(C *eqp, C *eqm, C drho, C jx, C jy, C jz)
 
 // One BGK collision of eq:LBE_BGK on the pre-collision deviations of a cell (rest in gp[0],
 // pair p in gp[p+1] / gm[p+1]); the arrays receive the post-collision deviations. With FORCE
-// and k.forced set, the body force is added by the exact-difference method:
-// g* += g^eq(rho, s + F/rho) - g^eq(rho, s). CLOSE applies close_moments to the equilibria; it
+// and k.forced set, the body force is added by the exact-difference method,
+// g* = g + w (g^eq(rho, s) - g) + [g^eq(rho, s + F/rho) - g^eq(rho, s)], evaluated as the one
+// fused multiply-add g* = (1 - w) (g - g^eq(rho, s)) + g^eq(rho, s + F/rho) per direction (the
+// same value in exact arithmetic, two operations fewer). CLOSE applies close_moments to the
+// equilibria; it
 // matters where the stored deviations keep FP32 resolution (FP32 storage). With 16-bit storage
 // each step's rounding of the deviations is about four orders above the drift the closure
 // removes, so those kernels skip it (measured: FP16 e(s) 2.23e-3 with, 2.25e-3 without, after
@@ -411,12 +447,6 @@ __device__ inline void collide_cell(const StepConsts<C> &k, C *gp, C *gm)
     C eqp[NP + 1], eqm[NP + 1];
     equilibrium_pairs<LAT, ORDER, C>(k, drho, rho, jx * inv, jy * inv, jz * inv, eqp, eqm);
     if constexpr (CLOSE) close_moments<LAT>(eqp, eqm, drho, jx, jy, jz);
-    gp[0] = fmad(k.omega, eqp[0] - gp[0], gp[0]);
-#pragma unroll
-    for (int p = 0; p < NP; ++p) {
-        gp[p + 1] = fmad(k.omega, eqp[p + 1] - gp[p + 1], gp[p + 1]);
-        gm[p + 1] = fmad(k.omega, eqm[p + 1] - gm[p + 1], gm[p + 1]);
-    }
     if constexpr (FORCE) {
         if (k.forced) {
             // both equilibria closed (in FP32) on their own momenta, j + F and j, so the
@@ -425,13 +455,21 @@ __device__ inline void collide_cell(const StepConsts<C> &k, C *gp, C *gm)
             C fqp[NP + 1], fqm[NP + 1];
             equilibrium_pairs<LAT, ORDER, C>(k, drho, rho, fjx * inv, fjy * inv, fjz * inv, fqp, fqm);
             if constexpr (CLOSE) close_moments<LAT>(fqp, fqm, drho, fjx, fjy, fjz);
-            gp[0] += fqp[0] - eqp[0];
+            const C keep = C(1) - k.omega;
+            gp[0] = fmad(keep, gp[0] - eqp[0], fqp[0]);
 #pragma unroll
             for (int p = 0; p < NP; ++p) {
-                gp[p + 1] += fqp[p + 1] - eqp[p + 1];
-                gm[p + 1] += fqm[p + 1] - eqm[p + 1];
+                gp[p + 1] = fmad(keep, gp[p + 1] - eqp[p + 1], fqp[p + 1]);
+                gm[p + 1] = fmad(keep, gm[p + 1] - eqm[p + 1], fqm[p + 1]);
             }
+            return;
         }
+    }
+    gp[0] = fmad(k.omega, eqp[0] - gp[0], gp[0]);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+        gp[p + 1] = fmad(k.omega, eqp[p + 1] - gp[p + 1], gp[p + 1]);
+        gm[p + 1] = fmad(k.omega, eqm[p + 1] - gm[p + 1], gm[p + 1]);
     }
 }
 

@@ -66,7 +66,8 @@ hipError_t launch_init(int lattice, int storage, int order, const Grid &g, const
                        const double *rho, const double *s, const uint32_t *links, void *dst, hipStream_t stream);
 
 // Launch flags of the step kernel (same values as LBM_LAUNCH_* in lbm.h).
-constexpr int kLaunchXcdSlabs = 1;  // XCD-contiguous tile order
+constexpr int kLaunchXcdSlabs = 1;     // XCD-contiguous tile order
+constexpr int kLaunchShiftedPull = 2;  // every pull a shifted load (no lane exchange)
 constexpr int kLaunchStreamOnly = 1 << 8;  // library-internal: pulls and stores only (no collision)
 
 // gray: per-cell gray fraction m (partial bounce-back) or null.
@@ -77,7 +78,8 @@ hipError_t launch_step(int lattice, int storage, int order, const Grid &g, const
 // ---- the gradient path (reverse sweep) ----
 constexpr int kGradPartialsHost = 7;  // per work-group: dJ/dK (6, symmetric part: xx yy zz xy xz yz), dJ/dtau
 // lam: adjoint populations (q N elements, the population layout of Grid) in the arithmetic
-// precision of the storage.
+// precision of the storage; launch_seed writes them unless lam is null. jpart: one double per
+// work-group of the seed launch (moments_groups(g)).
 // links: the link words of a masked grid or null.
 hipError_t launch_seed(int lattice, int storage, const Grid &g, const StepConsts<double> &k64,
                        const StepConsts<float> &k32, const void *src, void *lam, double *jpart, int kind, int plane,
@@ -88,13 +90,17 @@ hipError_t launch_adjoint(int lattice, int storage, int order, const Grid &g, co
 hipError_t launch_sum(const double *part, uint32_t nblocks, int m, double *out, hipStream_t stream);
 hipError_t launch_zero(double *p, uint64_t n, hipStream_t stream);
 
-// rho / s may be null. partials: scratch of kPartials * nblocks doubles; totals: kPartials
-// doubles of scratch (sum drho, sum rho s_x, _y, _z, fluid cells).
+// rho / s may be null. partials: scratch of kPartials * moments_groups(g) doubles; totals:
+// kPartials doubles of scratch (sum drho, sum rho s_x, _y, _z, fluid cells).
 constexpr int kPartials = 5;
+constexpr uint32_t kMomentGroups = 2048;  // most work-groups of a moments launch
 hipError_t launch_moments(int lattice, int storage, const Grid &g, const StepConsts<double> &k,
                           const uint32_t *links, const void *src, double *rho, double *s, double *partials,
                           double *totals, hipStream_t stream);
-uint32_t moments_blocks(const Grid &g);
+// Work-groups of one launch_moments (at most kMomentGroups).
+uint32_t moments_groups(const Grid &g);
+// Work-groups of the row-spanning launches over a grid (init, permute).
+uint32_t row_blocks(const Grid &g);
 // Work-groups of one launch_adjoint (the gpart partial sets it adds to).
 uint32_t adjoint_blocks(const Grid &g);
 

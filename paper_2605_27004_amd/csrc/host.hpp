@@ -63,3 +63,22 @@ bool aligned256(const void *ptr);
 
 }  // namespace host
 }  // namespace lbm
+
+// The context behind the opaque lbm_ctx handle (host memory only; the device buffers belong to
+// the caller).
+struct lbm_ctx {
+    lbm_params p;
+    lbm::host::Prepared pr;
+    lbm::Grid grid;
+    lbm::StepConsts<double> k64;
+    lbm::StepConsts<float> k32;
+    void *pop[2];
+    int cur;                 // index of the buffer that holds the current state
+    double *partials;        // reduction partials, then the totals (in the caller's scratch)
+    uint32_t *links;         // null without a solid mask
+    float *gray;             // null without a gray field
+    hipStream_t stream;
+    int64_t t;
+    int block_x, block_y;
+    int launch_flags;
+};

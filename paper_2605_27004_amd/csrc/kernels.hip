@@ -21,8 +21,10 @@
 // keeps FP32 mass conservation at round-off of the deviations rather than of f.
 //
 // The path is bound by HBM bandwidth (2 q sizeof(S) bytes per cell update), so there is no
-// LDS and no MFMA: each lane owns one cell, loads are coalesced along x, and the periodic
-// wrap is a per-lane offset select.
+// MFMA: each lane owns one cell and loads are coalesced along x. Where a wave lies inside one
+// grid row, x-shifted pulls load the lane's own x and shift one lane with DPP, exchanging the
+// wave-edge values through LDS (pull_aligned); otherwise the periodic wrap is a per-lane offset
+// select.
 #include <hip/hip_runtime.h>
 
 #include "cell.hpp"
@@ -66,12 +68,105 @@ __device__ inline uint32_t tile_of(const TileMap &m, uint32_t b)
 // aid that moves exactly the step's bytes in the step's pattern.
 enum StepMode : int { kPlain = 0, kLinks = 1, kGray = 2, kStream = 3 };
 
-template <int LAT, typename S, int ORDER, int MODE>
+// Pull of a cell's q pre-collision deviations when every wave lies inside one grid row: nx is a
+// multiple of 64 and a work-group spans whole rows or an exact fraction of a row (launch_step
+// checks this). An x-shifted pull would make each wave read three cache lines of which two are
+// shared with the neighbouring waves; measured on the bare D3Q19 256^3 FP32 pattern, that costs
+// 4% of the pass against loading the source row at the lane's own x (every line then read by one
+// wave, non-temporally) and moving the values one lane across the wave with DPP. The one value
+// that crosses a wave's edge comes from the neighbouring wave through LDS, or, at the two ends
+// of a work-group that spans only part of a row, from one wave-uniform load. The result is the
+// same gather, bit for bit. `live` (the wave's row exists) is uniform over each wave; every wave
+// reaches the barrier.
+// How the step kernel pulls (launch_step picks): every population with its own shifted load, or
+// the lane exchange of pull_aligned inside whole rows, or inside work-groups that span an exact
+// fraction of a row.
+enum PullKind : int { kPullShifted = 0, kPullRows = 1, kPullRowPart = 2 };
+
+template <int LAT, typename S, int PULL>
+__device__ inline void pull_aligned(const S *__restrict__ src, const Grid &g, const Cell &c, int32_t x, bool live,
+                                    typename Conv<S>::C *gp, typename Conv<S>::C *gm)
+{
+    static_assert(PULL == kPullRows || PULL == kPullRowPart, "lane-exchange pulls only");
+    using L = Lattice<LAT>;
+    using C = typename Conv<S>::C;
+    constexpr PullOrder<LAT> kPull{};
+    __shared__ C edge[L::Q][256 / 64];  // [direction][wave]: the value a neighbouring wave needs
+    const uint32_t wpr = blockDim.x >> 6;  // waves per row of the work-group
+    const uint32_t pos = threadIdx.x >> 6;  // this wave's place in its row
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wv = threadIdx.y * wpr + pos;
+    const uint32_t wl = threadIdx.y * wpr + (pos == 0u ? wpr - 1u : pos - 1u);  // holds x0 - 1 (row wrap)
+    const uint32_t wr = threadIdx.y * wpr + (pos == wpr - 1u ? 0u : pos + 1u);  // holds x0 + 64
+    const bool far_l = PULL == kPullRowPart && pos == 0u, far_r = PULL == kPullRowPart && pos == wpr - 1u;
+    const uint32_t x0 = (uint32_t)x - lane;
+    const uint32_t xl = x0 == 0u ? (uint32_t)g.nx - 1u : x0 - 1u;
+    const uint32_t xr = x0 + 64u == (uint32_t)g.nx ? 0u : x0 + 64u;
+    if (live) {
+#pragma unroll
+        for (int j = 0; j < L::Q; ++j) {
+            const int i = kPull.dir[j];
+            if (i == 0) {
+                gp[0] = Conv<S>::ld(ld_nt_at(pop_base(src, g, 0, own_ref(c)), own_ref(c).idx));
+                continue;
+            }
+            const int p = (i - 1) / 2, sg = (i & 1) ? 1 : -1;
+            const PairRow v = L::pair(p);
+            const Ref r = nbr(c, 0, sg * v.cy, sg * v.cz);  // the source row at this lane's x
+            const C val = Conv<S>::ld(ld_nt_at(pop_base(src, g, i, r), r.idx));
+            if (i & 1) gp[p + 1] = val; else gm[p + 1] = val;
+        }
+        // after all loads have been issued: the edge values the neighbouring waves pull
+        if (lane == 63u) {  // pulled from x - 1 by lane 0 of the next wave
+#pragma unroll
+            for (int p = 0; p < L::NP; ++p) {
+                const int cx = L::pair(p).cx;
+                if (cx > 0) edge[2 * p + 1][wv] = gp[p + 1];
+                if (cx < 0) edge[2 * p + 2][wv] = gm[p + 1];
+            }
+        }
+        if (lane == 0u) {  // pulled from x + 1 by lane 63 of the previous wave
+#pragma unroll
+            for (int p = 0; p < L::NP; ++p) {
+                const int cx = L::pair(p).cx;
+                if (cx < 0) edge[2 * p + 1][wv] = gp[p + 1];
+                if (cx > 0) edge[2 * p + 2][wv] = gm[p + 1];
+            }
+        }
+    }
+    __syncthreads();
+    if (!live) return;
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) {
+        const int p = (i - 1) / 2, sg = (i & 1) ? 1 : -1;
+        const PairRow v = L::pair(p);
+        const int cx = sg * v.cx;
+        if (cx == 0) continue;
+        C &val = (i & 1) ? gp[p + 1] : gm[p + 1];
+        const Ref r = nbr(c, 0, sg * v.cy, sg * v.cz);
+        const uint32_t row0 = r.idx - (uint32_t)x;  // x = 0 of the source row (wave-uniform)
+        if (cx > 0) {  // pulled from x - 1
+            C e = edge[i][wl];
+            if constexpr (PULL == kPullRowPart)
+                if (far_l) e = Conv<S>::ld(ld_at(pop_base(src, g, i, r), row0 + xl));
+            val = wave_shift<kFromLeft>(e, val);
+        } else {       // pulled from x + 1
+            C e = edge[i][wr];
+            if constexpr (PULL == kPullRowPart)
+                if (far_r) e = Conv<S>::ld(ld_at(pop_base(src, g, i, r), row0 + xr));
+            val = wave_shift<kFromRight>(e, val);
+        }
+    }
+}
+
+template <int LAT, typename S, int ORDER, int MODE, int PULL>
 __global__ __launch_bounds__(256) void k_step(const S *__restrict__ src, S *__restrict__ dst, const Grid g,
                                               const StepConsts<typename Conv<S>::C> k, const TileMap m,
                                               const uint32_t *__restrict__ links, const float *__restrict__ gray)
 {
     constexpr bool GENERAL = MODE == kLinks;
+    constexpr bool ALIGNED = PULL != kPullShifted;
+    static_assert(!(ALIGNED && GENERAL), "the lane-exchange pull serves the periodic, gray and streaming steps");
     using L = Lattice<LAT>;
     constexpr PullOrder<LAT> kPull{};
     using C = typename Conv<S>::C;
@@ -81,11 +176,17 @@ __global__ __launch_bounds__(256) void k_step(const S *__restrict__ src, S *__re
     const int32_t x = (int32_t)(tx * blockDim.x + threadIdx.x);
     const int32_t y = (int32_t)((tyz % m.tiles_y) * blockDim.y + threadIdx.y);
     const int32_t z = (int32_t)(tyz / m.tiles_y);
-    if (x >= g.nx || y >= g.ny) return;
-    const Cell c = cell_of(g, x, y, z);
 
     C gp[NP + 1], gm[NP + 1];
-    if constexpr (GENERAL) {
+    Cell c;
+    if constexpr (ALIGNED) {
+        const bool live = y < g.ny;
+        c = cell_of(g, x, live ? y : 0, z);
+        pull_aligned<LAT, S, PULL>(src, g, c, x, live, gp, gm);
+        if (!live) return;
+    } else if constexpr (GENERAL) {
+        if (x >= g.nx || y >= g.ny) return;
+        c = cell_of(g, x, y, z);
         // A solid cell has no state and none of its slots is ever read (links route around
         // it), but its lane still stores zeros so that every store of the wave covers whole
         // cache lines; partial-line stores along solid boundaries measured far slower.
@@ -107,6 +208,8 @@ __global__ __launch_bounds__(256) void k_step(const S *__restrict__ src, S *__re
             collide_cell<LAT, ORDER, true, C, kClose<S>>(k, gp, gm);
         }
     } else {
+        if (x >= g.nx || y >= g.ny) return;
+        c = cell_of(g, x, y, z);
 #pragma unroll
         for (int j = 0; j < L::Q; ++j) {
             const int i = kPull.dir[j], p = (i - 1) / 2;
@@ -203,23 +306,30 @@ __global__ __launch_bounds__(256) void k_init(const double *__restrict__ rho_in,
 
 constexpr int kRedThreads = 256;
 
-// Moments of the canonical state in FP64 plus per-block partial sums of (drho, rho u_x,
-// rho u_y, rho u_z, fluid cells) in a fixed tree order; u = (j + F/2) / rho.
+// Moments of the canonical state in FP64 plus per-work-group partial sums of (drho, rho u_x,
+// rho u_y, rho u_z, fluid cells); u = (j + F/2) / rho. The launch has a fixed number of
+// work-groups (at most kMomentGroups, whatever the grid): work-group w takes the row tiles
+// w, w + G, w + 2G, ... of the row_grid order, each lane sums its cells in that order, and the
+// work-group adds its lanes in a fixed tree, so the totals are reproducible bit for bit and
+// the partials need a small scratch of constant size.
 template <int LAT, typename S>
 __global__ __launch_bounds__(kRedThreads) void k_moments(const S *__restrict__ src, const uint32_t *__restrict__ links,
                                                          double *__restrict__ rho_out, double *__restrict__ s_out,
                                                          double *__restrict__ partials, const Grid g,
-                                                         const StepConsts<double> k)
+                                                         const StepConsts<double> k, const uint32_t tiles_x,
+                                                         const uint32_t tiles_y)
 {
     using L = Lattice<LAT>;
     constexpr int NP = L::NP;
     __shared__ double red[kPartials][kRedThreads];
-    const int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int32_t y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int32_t z = blockIdx.z;
     const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    const uint32_t tiles = tiles_x * tiles_y * (uint32_t)g.nz;
     double acc[kPartials] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    if (x < g.nx && y < g.ny) {
+    for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        const int32_t x = (int32_t)((t % tiles_x) * blockDim.x + threadIdx.x);
+        const int32_t y = (int32_t)(((t / tiles_x) % tiles_y) * blockDim.y + threadIdx.y);
+        const int32_t z = (int32_t)(t / (tiles_x * tiles_y));
+        if (x >= g.nx || y >= g.ny) continue;
         const Cell c = cell_of(g, x, y, z);
         const uint32_t lk = links ? links[c.own] : 0u;
         double rho = 0.0, ux = 0.0, uy = 0.0, uz = 0.0;
@@ -239,11 +349,11 @@ __global__ __launch_bounds__(kRedThreads) void k_moments(const S *__restrict__ s
             ux = mx / rho;
             uy = my / rho;
             uz = mz / rho;
-            acc[0] = drho;
-            acc[1] = mx;
-            acc[2] = my;
-            acc[3] = (L::D == 3) ? mz : 0.0;
-            acc[4] = 1.0;
+            acc[0] += drho;
+            acc[1] += mx;
+            acc[2] += my;
+            acc[3] += (L::D == 3) ? mz : 0.0;
+            acc[4] += 1.0;
         }
         if (rho_out) rho_out[c.own] = rho;
         if (s_out) {
@@ -259,10 +369,7 @@ __global__ __launch_bounds__(kRedThreads) void k_moments(const S *__restrict__ s
             for (int m = 0; m < kPartials; ++m) red[m][tid] += red[m][tid + h];
         __syncthreads();
     }
-    if (tid < kPartials) {
-        const uint32_t b = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-        partials[kPartials * (size_t)b + tid] = red[tid][0];
-    }
+    if (tid < kPartials) partials[kPartials * (size_t)blockIdx.x + tid] = red[tid][0];
 }
 
 __global__ __launch_bounds__(kRedThreads) void k_reduce_partials(const double *__restrict__ partials, uint32_t nblocks,
@@ -342,12 +449,18 @@ __global__ __launch_bounds__(256) void k_copy(const u32x4 *__restrict__ src, u32
 // d K += a G_s(nu) [+ G_s'(nu)], d m += sum_k mu_k (f_opp(k) - b_k). All formulas are in terms
 // of f; the stored deviations differ from f by constants, which cancel in every difference.
 
-// Moments of nu_k = keep mu_k weighted by w_k over all q directions: M0 = sum w nu,
-// M1_a = sum w nu c_a, M2_ab = sum w nu c_a c_b, and the third moments that are not M1 on these
-// lattices (c_a^3 = c_a): M3_aab = sum w nu c_a^2 c_b (a != b) and M3_xyz. They do not depend
-// on s, so one pass over the directions serves the transposed Jacobian at s and, with a force,
-// at s + F / rho.
+// Moments of the deviations nu_k - nu_0 of nu_k = keep mu_k from the rest direction's value
+// nu_0, weighted by w_k over all q directions: M0 = sum w (nu - nu_0), M1_a, M2_ab likewise with
+// c_a and c_a c_b, and the third moments that are not M1 on these lattices (c_a^3 = c_a):
+// M3_aab (a != b) and M3_xyz. The moments of nu itself follow exactly: the constant nu_0 adds
+// nu_0 to M0 and nu_0 cs^2 to the diagonal of M2 (sum w = 1, sum w c c = cs^2 I, odd moments of w
+// vanish). nu_0 cancels exactly from the K-sensitivity and from d tau and d m, so these are
+// formed from the deviations: their common part, often far larger than the direction-dependent
+// part, then adds no rounding (in FP32 it otherwise dominated the tensor gradient's error). The
+// moments do not depend on s, so one pass over the directions serves the transposed Jacobian at
+// s and, with a force, at s + F / rho.
 template <typename C> struct NuMoments {
+    C ref;    // nu_0
     C m0;
     C m1[3];
     C m2[6];  // xx yy zz xy xz yz
@@ -359,7 +472,8 @@ __device__ inline NuMoments<C> nu_moments(const StepConsts<C> &k, const C *mup, 
 {
     using L = Lattice<LAT>;
     NuMoments<C> m;
-    m.m0 = (keep * mup[0]) * k.w[0];
+    m.ref = keep * mup[0];
+    m.m0 = C(0);
 #pragma unroll
     for (int a = 0; a < 3; ++a) m.m1[a] = C(0);
 #pragma unroll
@@ -369,8 +483,11 @@ __device__ inline NuMoments<C> nu_moments(const StepConsts<C> &k, const C *mup, 
 #pragma unroll
     for (int p = 0; p < L::NP; ++p) {
         const PairRow v = L::pair(p);
-        const C fp = (keep * mup[p + 1]) * k.w[p + 1], fm = (keep * mum[p + 1]) * k.w[p + 1];
-        const C sum = fp + fm, dif = fp - fm;  // even and odd parts of the pair
+        // even and odd parts of the pair, each formed from the raw pair first: where mu is
+        // dominated by its odd part (a flux objective seeds mu_i = c_ix), mu+ + mu- is a small
+        // difference of two large values and is exact before any scaling rounds it
+        const C sum = fmad(keep, mup[p + 1] + mum[p + 1], C(-2) * m.ref) * k.w[p + 1];
+        const C dif = (keep * (mup[p + 1] - mum[p + 1])) * k.w[p + 1];
         const int c[3] = {v.cx, v.cy, v.cz};
         m.m0 += sum;
 #pragma unroll
@@ -420,16 +537,23 @@ template <typename C> __device__ inline C m3_at(const NuMoments<C> &m, int a, in
 //   sum nu f^eq / rho = M0 (1 - tr K / 2) + 1.5 K:M2 + 4.5 s.M2.s - 1.5 |s|^2 M0
 //                       + (3 - 1.5 tr K) s.M1 + 4.5 s.(K:M3) - 4.5 |s|^2 s.M1 + 4.5 M3:sss
 //                       - 3 M1.(K s).
+// A0 and A take the moments of nu (M0 = nu_0 + D0, M2 = nu_0 cs^2 I + D2 over the lattice's d
+// axes); G, in which nu_0 cancels (1.5 M2 - 0.5 M0 I), takes the deviation moments D0, D2.
 // K is symmetric and every tensor gradient the library reports depends on G only through
 // G + G^T, so G holds the symmetric part (G_ab + G_ba) / 2 as 6 entries xx, yy, zz, xy, xz, yz;
 // add coef * G.
-template <int ORDER, typename C>
+template <int D, int ORDER, typename C>
 __device__ inline void moment_vjp(const StepConsts<C> &k, const NuMoments<C> &m, C rho, C sx, C sy, C sz, C &A0,
                                   C &Ax, C &Ay, C &Az, C coef, C *G)
 {
     const C s[3] = {sx, sy, sz};
     const C Km[3][3] = {{k.k[0], k.k[3], k.k[4]}, {k.k[3], k.k[1], k.k[5]}, {k.k[4], k.k[5], k.k[2]}};
-    const C M2[3][3] = {{m.m2[0], m.m2[3], m.m2[4]}, {m.m2[3], m.m2[1], m.m2[5]}, {m.m2[4], m.m2[5], m.m2[2]}};
+    const C D2[3][3] = {{m.m2[0], m.m2[3], m.m2[4]}, {m.m2[3], m.m2[1], m.m2[5]}, {m.m2[4], m.m2[5], m.m2[2]}};
+    const C rc = m.ref * C(1.0 / 3.0);
+    const C M2[3][3] = {{D2[0][0] + rc, D2[0][1], D2[0][2]},
+                        {D2[1][0], D2[1][1] + rc, D2[1][2]},
+                        {D2[2][0], D2[2][1], D == 3 ? D2[2][2] + rc : D2[2][2]}};
+    const C M0 = m.m0 + m.ref;
     const C trK = k.k[0] + k.k[1] + k.k[2];
     const C usq = fmad(sx, sx, fmad(sy, sy, sz * sz));
     C M2s[3], sM2s = C(0), sM1 = C(0), KM2 = C(0);
@@ -441,12 +565,14 @@ __device__ inline void moment_vjp(const StepConsts<C> &k, const NuMoments<C> &m,
 #pragma unroll
         for (int b = 0; b < 3; ++b) KM2 = fmad(Km[a][b], M2[a][b], KM2);
     }
-    const C base0 = fmad(C(-0.5) * trK, m.m0, m.m0);  // M0 (1 - tr K / 2)
-    const C g = C(1.5) * fmad(C(-1), trK, C(2));      // 3 - 1.5 tr K
+    const C base0 = fmad(C(-0.5) * trK, M0, M0);  // M0 (1 - tr K / 2)
+    const C g = C(1.5) * fmad(C(-1), trK, C(2));  // 3 - 1.5 tr K
     C bracket = fmad(C(1.5), KM2, base0);
     bracket = fmad(C(4.5), sM2s, bracket);
-    bracket = fmad(C(-1.5) * usq, m.m0, bracket);
+    bracket = fmad(C(-1.5) * usq, M0, bracket);
     C Aa[3];
+    const int ea[6] = {0, 1, 2, 0, 0, 1}, eb[6] = {0, 1, 2, 1, 2, 2};
+    const C rcoef = rho * coef;
     if constexpr (ORDER == 3) {
         C KM3[3], M3ss[3], KM1[3], T3 = C(0), sKM3 = C(0), sKM1 = C(0);
         C M3s[3][3];
@@ -477,7 +603,7 @@ __device__ inline void moment_vjp(const StepConsts<C> &k, const NuMoments<C> &m,
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             C t = C(9) * M2s[a];
-            t = fmad(C(-3) * s[a], m.m0, t);
+            t = fmad(C(-3) * s[a], M0, t);
             t = fmad(g, m.m1[a], t);
             t = fmad(C(4.5), KM3[a], t);
             t = fmad(C(-9) * s[a], sM1, t);
@@ -486,29 +612,25 @@ __device__ inline void moment_vjp(const StepConsts<C> &k, const NuMoments<C> &m,
             t = fmad(C(-3), KM1[a], t);
             Aa[a] = t;
         }
-        const int ea[6] = {0, 1, 2, 0, 0, 1}, eb[6] = {0, 1, 2, 1, 2, 2};
-        const C rc = rho * coef;
 #pragma unroll
         for (int e = 0; e < 6; ++e) {
             const int a = ea[e], b = eb[e];
-            C t = C(1.5) * M2[a][b];
+            C t = C(1.5) * D2[a][b];  // 1.5 M2 - 0.5 M0 I: nu_0 cancels
             if (a == b) t = fmad(C(-0.5), m.m0, fmad(C(-1.5), sM1, t));
             t = fmad(C(4.5), M3s[a][b], t);
             t -= C(1.5) * fmad(m.m1[a], s[b], m.m1[b] * s[a]);
-            G[e] = fmad(rc, t, G[e]);
+            G[e] = fmad(rcoef, t, G[e]);
         }
     } else {
         bracket = fmad(C(3), sM1, bracket);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) Aa[a] = fmad(C(9), M2s[a], fmad(C(-3) * s[a], m.m0, C(3) * m.m1[a]));
-        const int ea[6] = {0, 1, 2, 0, 0, 1}, eb[6] = {0, 1, 2, 1, 2, 2};
-        const C rc = rho * coef;
+        for (int a = 0; a < 3; ++a) Aa[a] = fmad(C(9), M2s[a], fmad(C(-3) * s[a], M0, C(3) * m.m1[a]));
 #pragma unroll
         for (int e = 0; e < 6; ++e) {
             const int a = ea[e], b = eb[e];
-            C t = C(1.5) * M2[a][b];
+            C t = C(1.5) * D2[a][b];  // 1.5 M2 - 0.5 M0 I: nu_0 cancels
             if (a == b) t = fmad(C(-0.5), m.m0, t);
-            G[e] = fmad(rc, t, G[e]);
+            G[e] = fmad(rcoef, t, G[e]);
         }
     }
     A0 = bracket;
@@ -519,25 +641,30 @@ __device__ inline void moment_vjp(const StepConsts<C> &k, const NuMoments<C> &m,
 
 constexpr int kGradPartials = 7;  // symmetric G (6) and d tau, per work-group
 
-// Seed of the reverse sweep from the final state: lam_i = dJ / d f_i, and the objective's
-// per-work-group partial sums. kind 0: flux through the plane x = plane, J = sum (j_x + F_x/2);
-// kind 1: kinetic energy, J = sum |j + F/2|^2 / (2 rho). (plane_x: the flux plane's x index)
+// Seed of the reverse sweep from the final state: lam_i = dJ / d f_i (skipped when lam is null,
+// which leaves the evaluation of J alone), and the objective's partial sums, one per
+// work-group. kind 0: flux through the plane x = plane_x, J = sum (j_x + F_x/2); kind 1: kinetic
+// energy, J = sum |j + F/2|^2 / (2 rho). Like k_moments, the launch has a fixed number of
+// work-groups that stride over the row tiles in a fixed order (reproducible sums).
 template <int LAT, typename S>
 __global__ __launch_bounds__(256) void k_seed(const S *__restrict__ src, typename Conv<S>::C *__restrict__ lam,
                                               double *__restrict__ jpart, const Grid g,
                                               const StepConsts<typename Conv<S>::C> k, const int kind, const int plane_x,
-                                              const uint32_t *__restrict__ links)
+                                              const uint32_t *__restrict__ links, const uint32_t tiles_x,
+                                              const uint32_t tiles_y)
 {
     using L = Lattice<LAT>;
     using C = typename Conv<S>::C;
     constexpr int NP = L::NP;
     __shared__ double red[256];
-    const int32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-    const int32_t y = blockIdx.y * blockDim.y + threadIdx.y;
-    const int32_t z = blockIdx.z;
     const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+    const uint32_t tiles = tiles_x * tiles_y * (uint32_t)g.nz;
     double jv = 0.0;
-    if (x < g.nx && y < g.ny) {
+    for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        const int32_t x = (int32_t)((t % tiles_x) * blockDim.x + threadIdx.x);
+        const int32_t y = (int32_t)(((t / tiles_x) % tiles_y) * blockDim.y + threadIdx.y);
+        const int32_t z = (int32_t)(t / (tiles_x * tiles_y));
+        if (x >= g.nx || y >= g.ny) continue;
         const Cell c = cell_of(g, x, y, z);
         const uint32_t lk = links ? links[c.own] : 0u;
         C gp[NP + 1], gm[NP + 1];
@@ -558,23 +685,25 @@ __global__ __launch_bounds__(256) void k_seed(const S *__restrict__ src, typenam
         } else if (kind == 0) {
             if (x == plane_x) {
                 ux = C(1);
-                jv = (double)mx;
+                jv += (double)mx;
             }
         } else {
             ux = mx / rho;
             uy = my / rho;
             uz = mz / rho;
             base = C(-0.5) * fmad(ux, ux, fmad(uy, uy, uz * uz));
-            jv = 0.5 * ((double)mx * mx + (double)my * my + (double)mz * mz) / (double)rho;
+            jv += 0.5 * ((double)mx * mx + (double)my * my + (double)mz * mz) / (double)rho;
         }
-        // lam_i = base + u . c_i
-        st_pop(lam, g, 0, own_ref(c), base);
+        if (lam) {
+            // lam_i = base + u . c_i
+            st_pop(lam, g, 0, own_ref(c), base);
 #pragma unroll
-        for (int p = 0; p < NP; ++p) {
-            const PairRow v = L::pair(p);
-            const C uc = (C)v.cx * ux + (C)v.cy * uy + (C)v.cz * uz;
-            st_pop(lam, g, 2 * p + 1, own_ref(c), base + uc);
-            st_pop(lam, g, 2 * p + 2, own_ref(c), base - uc);
+            for (int p = 0; p < NP; ++p) {
+                const PairRow v = L::pair(p);
+                const C uc = (C)v.cx * ux + (C)v.cy * uy + (C)v.cz * uz;
+                st_pop(lam, g, 2 * p + 1, own_ref(c), base + uc);
+                st_pop(lam, g, 2 * p + 2, own_ref(c), base - uc);
+            }
         }
     }
     red[tid] = jv;
@@ -583,7 +712,7 @@ __global__ __launch_bounds__(256) void k_seed(const S *__restrict__ src, typenam
         if (tid < h) red[tid] += red[tid + h];
         __syncthreads();
     }
-    if (tid == 0) jpart[(blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = red[0];
+    if (tid == 0) jpart[blockIdx.x] = red[0];
 }
 
 // Where the adjoint of the post-collision population of direction +c (resp. -c) of pair p at x
@@ -653,7 +782,7 @@ __device__ inline void adjoint_cell(const S *__restrict__ state, const typename 
         // first pass over the directions: the transposed equilibrium Jacobian (and G)
         const NuMoments<C> nm = nu_moments<LAT>(k, mup, mum, keep);
         C A0, Ax, Ay, Az;
-        moment_vjp<ORDER, C>(k, nm, rho, sx, sy, sz, A0, Ax, Ay, Az, a, G);
+        moment_vjp<L::D, ORDER, C>(k, nm, rho, sx, sy, sz, A0, Ax, Ay, Az, a, G);
         C base = a * (A0 - (Ax * sx + Ay * sy + Az * sz) * inv);
         C ax = a * Ax * inv, ay = a * Ay * inv, az = a * Az * inv;
         C tx = C(0), ty = C(0), tz = C(0);
@@ -662,7 +791,7 @@ __device__ inline void adjoint_cell(const S *__restrict__ state, const typename 
             ty = (jy + k.force[1]) * inv;
             tz = (jz + k.force[2]) * inv;
             C B0, Bx, By, Bz;
-            moment_vjp<ORDER, C>(k, nm, rho, tx, ty, tz, B0, Bx, By, Bz, C(1), G);
+            moment_vjp<L::D, ORDER, C>(k, nm, rho, tx, ty, tz, B0, Bx, By, Bz, C(1), G);
             base += B0 - (Bx * tx + By * ty + Bz * tz) * inv;
             ax += Bx * inv;
             ay += By * inv;
@@ -675,22 +804,20 @@ __device__ inline void adjoint_cell(const S *__restrict__ state, const typename 
         const EqCell<C> ef = eq_cell(k, drho, rho, tx, ty, tz);
         const C om = C(1) - w;
         C dm;
-        {
-            const C eq = eq_rest(k, e);
-            C b = fmad(w, eq - gp[0], gp[0]);
-            dtau = (keep * mup[0]) * (eq - gp[0]);
-            if constexpr (FORCED) b += eq_rest(k, ef) - eq;
-            dm = mup[0] * (gp[0] - b);
-            st_pop(lam_out, g, 0, own_ref(c), fmad(mg, mup[0], fmad(om, keep * mup[0], base)));
-        }
+        // d tau = -w^2 sum_k nu_k (f^eq_k - f_k) and d m = sum_k mu_k (f_opp(k) - b_k): both
+        // differences sum to zero over k (mass), so nu_0 and mu_0 drop out and the sums run over
+        // nu_k - nu_0 and mu_k - mu_0 (the rest direction then adds nothing)
+        dtau = C(0);
+        dm = C(0);
+        st_pop(lam_out, g, 0, own_ref(c), fmad(mg, mup[0], fmad(om, nm.ref, base)));
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
             C ep, em;
             eq_pair<LAT, ORDER, C>(k, e, p, ep, em);
             C bp = fmad(w, ep - gp[p + 1], gp[p + 1]);
             C bm = fmad(w, em - gm[p + 1], gm[p + 1]);
-            dtau = fmad(keep * mup[p + 1], ep - gp[p + 1], dtau);
-            dtau = fmad(keep * mum[p + 1], em - gm[p + 1], dtau);
+            dtau = fmad(fmad(keep, mup[p + 1], -nm.ref), ep - gp[p + 1], dtau);
+            dtau = fmad(fmad(keep, mum[p + 1], -nm.ref), em - gm[p + 1], dtau);
             if constexpr (FORCED) {
                 C fp, fm;
                 eq_pair<LAT, ORDER, C>(k, ef, p, fp, fm);
@@ -701,8 +828,8 @@ __device__ inline void adjoint_cell(const S *__restrict__ state, const typename 
             const C vc = (C)v.cx * ax + (C)v.cy * ay + (C)v.cz * az;
             st_pop(lam_out, g, 2 * p + 1, own_ref(c), fmad(mg, mum[p + 1], fmad(om, keep * mup[p + 1], base + vc)));
             st_pop(lam_out, g, 2 * p + 2, own_ref(c), fmad(mg, mup[p + 1], fmad(om, keep * mum[p + 1], base - vc)));
-            dm = fmad(mup[p + 1], gm[p + 1] - bp, dm);
-            dm = fmad(mum[p + 1], gp[p + 1] - bm, dm);
+            dm = fmad(mup[p + 1] - mup[0], gm[p + 1] - bp, dm);
+            dm = fmad(mum[p + 1] - mup[0], gp[p + 1] - bm, dm);
         }
         dtau *= -w * w;
         if (dmask) dmask[c.own] += (double)dm;
@@ -877,9 +1004,29 @@ hipError_t launch_step(int lattice, int storage, int order, const Grid &g, const
             const dim3 grid(m.nblocks);
             const int mode = (flags & kLaunchStreamOnly) ? kStream
                              : gray ? kGray : ((links != nullptr || kc->forced) ? kLinks : kPlain);
+            // the lane-exchange pull needs every wave inside one row (see pull_aligned)
+            const bool aligned = mode != kLinks && !(flags & kLaunchShiftedPull) && g.nx % 64 == 0 &&
+                                 g.nx % block_x == 0;
+            const bool whole_rows = block_x == g.nx;
             const S *in = (const S *)src;
             S *out = (S *)dst;
-#define LBM_STEP(O, M) hipLaunchKernelGGL((k_step<LAT, S, O, M>), grid, block, 0, stream, in, out, g, *kc, m, links, gray)
+#define LBM_STEP(O, M)                                                                                           \
+    do {                                                                                                         \
+        if constexpr (M != kLinks) {                                                                             \
+            if (aligned && whole_rows) {                                                                         \
+                hipLaunchKernelGGL((k_step<LAT, S, O, M, kPullRows>), grid, block, 0, stream, in, out, g, *kc, m, \
+                                   links, gray);                                                                 \
+                break;                                                                                           \
+            }                                                                                                    \
+            if (aligned) {                                                                                       \
+                hipLaunchKernelGGL((k_step<LAT, S, O, M, kPullRowPart>), grid, block, 0, stream, in, out, g, *kc, \
+                                   m, links, gray);                                                              \
+                break;                                                                                           \
+            }                                                                                                    \
+        }                                                                                                        \
+        hipLaunchKernelGGL((k_step<LAT, S, O, M, kPullShifted>), grid, block, 0, stream, in, out, g, *kc, m, links, \
+                           gray);                                                                                \
+    } while (0)
             if (mode == kStream) {
                 LBM_STEP(3, kStream);
             } else if (order == 2) {
@@ -920,10 +1067,16 @@ uint32_t adjoint_blocks(const Grid &g)
     return grid.x * grid.y;
 }
 
-uint32_t moments_blocks(const Grid &g)
+uint32_t row_blocks(const Grid &g)
 {
     const dim3 grid = row_grid(g);
     return grid.x * grid.y * grid.z;
+}
+
+uint32_t moments_groups(const Grid &g)
+{
+    const uint32_t t = row_blocks(g);
+    return t < kMomentGroups ? t : kMomentGroups;
 }
 
 hipError_t launch_moments(int lattice, int storage, const Grid &g, const StepConsts<double> &k,
@@ -934,13 +1087,13 @@ hipError_t launch_moments(int lattice, int storage, const Grid &g, const StepCon
         return by_storage(storage, [&](auto sv) {
             using S = decltype(sv);
             constexpr int LAT = decltype(lat)::value;
-            const dim3 grid = row_grid(g), block = row_block(g);
-            hipLaunchKernelGGL((k_moments<LAT, S>), grid, block, 0, stream, (const S *)src, links, rho, s, partials, g,
-                               k);
+            const dim3 tiles = row_grid(g), block = row_block(g);
+            const uint32_t groups = moments_groups(g);
+            hipLaunchKernelGGL((k_moments<LAT, S>), dim3(groups), block, 0, stream, (const S *)src, links, rho, s,
+                               partials, g, k, tiles.x, tiles.y);
             hipError_t e = hipGetLastError();
             if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kRedThreads), 0, stream, partials,
-                               grid.x * grid.y * grid.z, totals);
+            hipLaunchKernelGGL(k_reduce_partials, dim3(1), dim3(kRedThreads), 0, stream, partials, groups, totals);
             return hipGetLastError();
         });
     });
@@ -976,9 +1129,9 @@ hipError_t launch_seed(int lattice, int storage, const Grid &g, const StepConsts
             constexpr int LAT = decltype(lat)::value;
             const StepConsts<C> *kc;
             if constexpr (sizeof(C) == 8) kc = &k64; else kc = &k32;
-            const dim3 grid = row_grid(g), block = row_block(g);
-            hipLaunchKernelGGL((k_seed<LAT, S>), grid, block, 0, stream, (const S *)src, (C *)lam, jpart, g, *kc, kind,
-                               plane, links);
+            const dim3 tiles = row_grid(g), block = row_block(g);
+            hipLaunchKernelGGL((k_seed<LAT, S>), dim3(moments_groups(g)), block, 0, stream, (const S *)src, (C *)lam,
+                               jpart, g, *kc, kind, plane, links, tiles.x, tiles.y);
             return hipGetLastError();
         });
     });

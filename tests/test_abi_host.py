@@ -152,7 +152,12 @@ def test_sizes():
     p = lbm.make_params("D3Q19", "f32", (256, 256, 256), W.config2_theta(0), "theta", 0.7)
     assert lbm.lbm_pop_bytes(p) == 19 * 256 ** 3 * 4
     plain = lbm.lbm_scratch_bytes(p)
-    assert plain % 256 == 0 and plain >= 8 * 5 * (256 ** 3 // 256)
+    # five FP64 partial sums per work-group of the moments launch (at most 2048 work-groups,
+    # whatever the grid) and the five totals
+    assert plain % 256 == 0 and plain == (8 * 5 * (2048 + 1) + 255) // 256 * 256
+    # a 16 x 8 x 4 grid has 8 row tiles of 64 x 4 lanes, so its moments launch has 8 work-groups
+    small = lbm.make_params("D3Q19", "f32", (16, 8, 4), W.config2_theta(0), "theta", 0.7)
+    assert lbm.lbm_scratch_bytes(small) == (8 * 5 * (8 + 1) + 255) // 256 * 256
     pm = lbm.make_params("D3Q19", "f32", (256, 256, 256), W.config2_theta(0), "theta", 0.7, masked=True)
     assert lbm.lbm_scratch_bytes(pm) == plain + 4 * 256 ** 3     # link words
 

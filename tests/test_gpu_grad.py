@@ -201,13 +201,17 @@ def test_checkpoint_interval_does_not_change_gradients(ckpt):
 
 
 def test_fp32_adjoint_close_to_fp64():
+    """FP32 storage against the library's FP64 path (which matches oracle finite differences
+    to 1e-6) on every output, at the FP32 gate of the step count."""
     c = _case("D3Q19", (10, 8, 6))
-    a = _gpu(c, "f64", 40, "kinetic_energy", 0, 10)
-    b = _gpu(c, "f32", 40, "kinetic_energy", 0, 10)
-    assert abs(b[0] - a[0]) <= 1e-5 * abs(a[0])
-    assert np.abs(b[1] - a[1]).max() <= 1e-3 * np.abs(a[1]).max()
-    assert abs(b[2] - a[2]) <= 1e-3 * abs(a[2])
-    assert np.abs(b[3] - a[3]).max() <= 1e-3 * np.abs(a[3]).max()
+    steps = 40
+    a = _gpu(c, "f64", steps, "kinetic_energy", 0, 10)
+    b = _gpu(c, "f32", steps, "kinetic_energy", 0, 10)
+    e = [abs(b[0] - a[0]) / abs(a[0]), np.abs(b[1] - a[1]).max() / np.abs(a[1]).max(),
+         abs(b[2] - a[2]) / abs(a[2]), np.abs(b[3] - a[3]).max() / np.abs(a[3]).max()]
+    print(f"[grad32] f32 vs f64 T={steps}: J {e[0]:.2e} dT {e[1]:.2e} dtau {e[2]:.2e} dm {e[3]:.2e} "
+          f"(gate {_tol32(steps):.2e})", flush=True)
+    assert max(e) <= _tol32(steps)
 
 
 def test_grad_advances_like_step():
@@ -303,20 +307,201 @@ def test_binary_mask_adjoint_matches_oracle_finite_differences(lattice, shape, o
         assert close(dm[cell], fd), (cell, dm[cell], fd)
 
 
+def _objective_cfg(c, nsteps=12, objective="kinetic_energy"):
+    return dict(lattice=c["lattice"], storage="f64", shape=c["shape"], rho=c["rho"], s=c["s"], force=c["force"],
+                objective=objective, nsteps=nsteps, checkpoint_every=5, outlet_plane=1)
+
+
 def test_autograd_function():
+    """Objective as a torch function: J and the gradients of lbm_grad, scaled by backward; the
+    tensor's off-diagonal elements each get half of lbm_grad's symmetric-direction derivative
+    (the update uses (T + T^T) / 2). Inputs on the GPU get their gradients on the GPU."""
     c = _case("D2Q9", (10, 8, 1))
-    fn = lbm.Objective.function()
-    cfg = dict(lattice="D2Q9", storage="f64", shape=c["shape"], rho=c["rho"], s=c["s"], force=c["force"],
-               objective="kinetic_energy", nsteps=12, checkpoint_every=5)
-    tensor = torch.tensor(c["tensor"], dtype=torch.float64, requires_grad=True)
-    tau = torch.tensor(0.8, dtype=torch.float64, requires_grad=True)
+    obj = lbm.Objective(_objective_cfg(c))
+    tensor = torch.tensor(c["tensor"][:2, :2], dtype=torch.float64, device="cuda", requires_grad=True)
+    tau = torch.tensor(0.8, dtype=torch.float64, device="cuda", requires_grad=True)
     gray = torch.tensor(c["gray"], dtype=torch.float32, device="cuda", requires_grad=True)
-    j = fn.apply(tensor, tau, gray, cfg)
+    j = obj(tensor, tau, gray)
     (2.0 * j).backward()
     j2, dt, du, dm = _gpu(c, "f64", 12, "kinetic_energy", 0, 5)
-    assert float(j) == j2
-    assert np.allclose(tensor.grad.numpy(), 2 * dt) and abs(float(tau.grad) - 2 * du) < 1e-15
+    assert float(j.detach()) == j2
+    half = np.where(np.eye(2, dtype=bool), 1.0, 0.5)
+    assert tensor.grad.device.type == "cuda" and tau.grad.device.type == "cuda"
+    assert np.allclose(tensor.grad.cpu().numpy(), 2 * dt[:2, :2] * half, rtol=1e-14, atol=0)
+    assert abs(float(tau.grad) - 2 * du) <= 1e-14 * abs(du)
     assert np.allclose(gray.grad.cpu().numpy(), 2 * dm, rtol=1e-6)
+    assert obj.adjoint_calls == 1 and obj.forward_calls == 0
+
+
+@pytest.mark.parametrize("lattice,shape,objective", [("D2Q9", (9, 7, 1), "flux"), ("D3Q19", (6, 5, 4), "kinetic_energy")])
+def test_autograd_symmetric_parameter_matches_oracle(lattice, shape, objective):
+    """A scalar theta placed in both off-diagonal slots (x, y) of the tensor: dJ/dtheta through
+    autograd's chain rule against central differences of the FP64 oracle."""
+    c = _case(lattice, shape)
+    d = c["d"]
+    steps = 14
+    obj = lbm.Objective(_objective_cfg(c, steps, objective))
+    base = torch.tensor(c["tensor"][:d, :d], dtype=torch.float64)
+    theta = torch.tensor(float(c["tensor"][0, 1]), dtype=torch.float64, requires_grad=True)
+    e01 = torch.zeros(d, d, dtype=torch.float64)
+    e01[0, 1] = e01[1, 0] = 1.0
+    t = base * (1 - e01) + theta * e01
+    j = obj(t, 0.8, None)
+    j.backward()
+    g = float(theta.grad)
+    ainv0 = oracle.tensor_to_ainv(c["tensor"][:d, :d], "theta", d)
+    zero = np.zeros(int(np.prod(shape)))
+    cc = dict(c, kind="theta")
+
+    def oj(v):
+        tt = c["tensor"].copy()
+        tt[0, 1] = tt[1, 0] = v
+        return _oracle_J(cc, tt, 0.8, zero, steps, objective, 1, ainv0)
+
+    h = 1e-5
+    v0 = float(c["tensor"][0, 1])
+    fd = (oj(v0 + h) - oj(v0 - h)) / (2 * h)
+    print(f"[grad] autograd dJ/dtheta {g:.12e} oracle fd {fd:.12e}", flush=True)
+    assert abs(g - fd) <= 1e-6 * abs(fd) + 1e-9 * abs(float(j))
+
+
+def test_objective_without_grad_runs_no_adjoint():
+    """Under torch.no_grad (or with no input requiring a gradient) the call is one forward
+    pass and lbm_objective: the same J as lbm_grad's, no adjoint, and the device buffers of the
+    first call are reused by the next."""
+    c = _case("D3Q19", (12, 9, 7))
+    obj = lbm.Objective(_objective_cfg(c, 15, "flux"))
+    tensor = torch.tensor(c["tensor"], dtype=torch.float64, requires_grad=True)
+    with torch.no_grad():
+        j1 = obj(tensor, 0.8)
+    ptr = obj._bufs["pop_a"].data_ptr()
+    j2 = obj(tensor.detach(), 0.8)
+    assert obj.adjoint_calls == 0 and obj.forward_calls == 2
+    assert obj._bufs["pop_a"].data_ptr() == ptr
+    jg = obj(tensor, 0.8)
+    assert obj.adjoint_calls == 1
+    assert float(j1) == float(j2) == float(jg.detach())
+
+
+# FP32 storage (the gradient workload's precision: FP32 forward and adjoint populations, FP64
+# parameter sums) against central differences of the FP64 oracle. Gate per group of outputs
+# (J; tensor entries; tau; sampled dm), relative to the group's largest reference value:
+#     tol32 = kappa T u32,  u32 = 2^-24, T the number of steps.
+# Each step rounds the stored deviations, the adjoint populations and the per-cell arithmetic
+# once, relative to the adjoint's own magnitude, and those errors add up at worst linearly over T
+# steps. kappa is the ratio of that magnitude to the reported derivative (the derivative's
+# conditioning): 1 on the gradient workload itself, 4 for the kinetic-energy objective on
+# random fields, 32 for the outlet flux on random fields, whose tensor derivative is a small
+# residual of the adjoint's terms (measured with an FP64-arithmetic build of the same adjoint on
+# FP32 storage: every stage of the FP32 adjoint contributes, no single term dominates).
+KAPPA = {"kinetic_energy": 4.0, "flux": 32.0}
+
+
+def _tol32(steps, kappa=1.0):
+    return kappa * steps * 2.0 ** -24
+
+
+FP32_CASES = [("D2Q9", (16, 12, 1), "theta", "flux"), ("D3Q19", (8, 6, 5), "A", "kinetic_energy"),
+              ("D3Q27", (7, 6, 5), "theta", "kinetic_energy")]
+
+
+@pytest.mark.parametrize("case", FP32_CASES, ids=lambda c: "-".join(str(v) for v in c))
+def test_fp32_adjoint_matches_oracle_finite_differences(case):
+    lattice, shape, kind, objective = case
+    c = _case(lattice, shape, kind)
+    steps, ckpt, plane = 23, 5, 3
+    d = c["d"]
+    gray = c["gray"].astype(np.float32).astype(np.float64)
+    c["gray"] = gray
+    ainv0 = oracle.tensor_to_ainv(c["tensor"][:d, :d], kind, d)
+    j, dt, du, dm = _gpu(c, "f32", steps, objective, plane, ckpt)
+    j0 = _oracle_J(c, c["tensor"], c["tau"], gray, steps, objective, plane, ainv0)
+    fdt = np.zeros((d, d))
+    for a in range(d):
+        for b in range(a, d):
+            h = 1e-5
+            tp = c["tensor"].copy(); tm = c["tensor"].copy()
+            tp[a, b] += h; tm[a, b] -= h
+            if a != b:
+                tp[b, a] += h; tm[b, a] -= h
+            fdt[a, b] = fdt[b, a] = (_oracle_J(c, tp, c["tau"], gray, steps, objective, plane, ainv0)
+                                     - _oracle_J(c, tm, c["tau"], gray, steps, objective, plane, ainv0)) / (2 * h)
+    h = 1e-5
+    fdu = (_oracle_J(c, c["tensor"], c["tau"] + h, gray, steps, objective, plane, ainv0)
+           - _oracle_J(c, c["tensor"], c["tau"] - h, gray, steps, objective, plane, ainv0)) / (2 * h)
+    cells = np.random.default_rng(7).choice(len(gray), 4, replace=False)
+    fdm = []
+    for cell in cells:
+        def central(hh):
+            gp = gray.copy(); gm = gray.copy()
+            gp[cell] += hh; gm[cell] -= hh
+            return (_oracle_J(c, c["tensor"], c["tau"], gp, steps, objective, plane, ainv0)
+                    - _oracle_J(c, c["tensor"], c["tau"], gm, steps, objective, plane, ainv0)) / (2 * hh)
+        fdm.append((4.0 * central(5e-5) - central(1e-4)) / 3.0)
+    fdm = np.array(fdm)
+    e_j = abs(j - j0) / abs(j0)
+    e_t = np.abs(dt[:d, :d] - fdt).max() / np.abs(fdt).max()
+    e_u = abs(du - fdu) / abs(fdu)
+    e_m = np.abs(dm[cells] - fdm).max() / np.abs(fdm).max()
+    tol = _tol32(steps, KAPPA[objective])
+    print(f"[grad32] {lattice} {kind} {objective} T={steps}: J {e_j:.2e} dT {e_t:.2e} dtau {e_u:.2e} "
+          f"dm {e_m:.2e} (gate {tol:.2e})", flush=True)
+    assert e_j <= tol and e_t <= tol and e_u <= tol and e_m <= tol
+
+
+@pytest.mark.parametrize("lattice,shape,objective", [("D2Q9", (15, 11, 1), "flux"), ("D3Q19", (8, 7, 6), "kinetic_energy")])
+def test_fp32_binary_mask_adjoint_matches_oracle_finite_differences(lattice, shape, objective):
+    """Halfway bounce-back walls, FP32 storage: tensor entries, tau and dJ/dm at m = 0 on fluid
+    cells against central differences of the FP64 oracle, at the FP32 gate."""
+    c = _case(lattice, shape)
+    d = c["d"]
+    n = int(np.prod(shape))
+    rng = np.random.default_rng(21)
+    mask = (rng.uniform(size=n) < 0.2).astype(np.uint8)
+    steps, ckpt, plane = 21, 6, 2
+    ainv0 = oracle.tensor_to_ainv(c["tensor"][:d, :d], "theta", d)
+
+    def oracle_J(tensor, tau, gray):
+        f = oracle.init(lattice, shape, ainv0, c["rho"], c["s"], mask=mask)
+        ainv = oracle.tensor_to_ainv(np.asarray(tensor)[:d, :d], "theta", d)
+        oracle.steps_gray(lattice, shape, ainv, tau, f, steps, gray, force=c["force"], mask=mask)
+        return oracle.objective(lattice, shape, f, 0 if objective == "flux" else 1, plane, mask=mask,
+                                force=c["force"])
+
+    p = lbm.make_params(lattice, "f32", shape, c["tensor"], "theta", c["tau"], force=c["force"], masked=True)
+    sim = lbm.Simulation(p, c["rho"], c["s"], mask=mask)
+    j, dt, du, dm = sim.grad(objective, steps, ckpt, plane)
+    dt, dm = np.array(dt), dm.cpu().numpy()
+    zero = np.zeros(n)
+    j0 = oracle_J(c["tensor"], c["tau"], zero)
+    fdt = np.zeros((d, d))
+    for a in range(d):
+        for b in range(a, d):
+            h = 1e-5
+            tp = c["tensor"].copy(); tm = c["tensor"].copy()
+            tp[a, b] += h; tm[a, b] -= h
+            if a != b:
+                tp[b, a] += h; tm[b, a] -= h
+            fdt[a, b] = fdt[b, a] = (oracle_J(tp, c["tau"], zero) - oracle_J(tm, c["tau"], zero)) / (2 * h)
+    h = 1e-5
+    fdu = (oracle_J(c["tensor"], c["tau"] + h, zero) - oracle_J(c["tensor"], c["tau"] - h, zero)) / (2 * h)
+    cells = rng.choice(np.flatnonzero(mask == 0), 4, replace=False)
+    fdm = []
+    for cell in cells:
+        h = 1e-4
+        gp = zero.copy(); gm = zero.copy()
+        gp[cell] = h; gm[cell] = -h
+        fdm.append((oracle_J(c["tensor"], c["tau"], gp) - oracle_J(c["tensor"], c["tau"], gm)) / (2 * h))
+    fdm = np.array(fdm)
+    e_j = abs(j - j0) / abs(j0)
+    e_t = np.abs(dt[:d, :d] - fdt).max() / np.abs(fdt).max()
+    e_u = abs(du - fdu) / abs(fdu)
+    e_m = np.abs(dm[cells] - fdm).max() / np.abs(fdm).max()
+    tol = _tol32(steps, KAPPA[objective])
+    print(f"[grad32] masked {lattice} {objective} T={steps}: J {e_j:.2e} dT {e_t:.2e} dtau {e_u:.2e} "
+          f"dm {e_m:.2e} (gate {tol:.2e})", flush=True)
+    assert np.all(dm[mask == 1] == 0.0)
+    assert e_j <= tol and e_t <= tol and e_u <= tol and e_m <= tol
 
 
 @pytest.mark.parametrize("lattice", ["D2Q9", "D3Q19"])
@@ -372,5 +557,10 @@ def test_gradient_workload_full_size(lattice):
     dm32 = dm32.cpu().numpy()
     print(f"[grad] {lattice} f32 vs f64: J {abs(j32 / j - 1):.2e} dtau {abs(du32 / du - 1):.2e} "
           f"dm {np.abs(dm32 - dm).max() / np.abs(dm).max():.2e}", flush=True)
-    assert abs(j32 / j - 1) < 1e-4 and abs(du32 / du - 1) < 1e-2
-    assert np.abs(dm32 - dm).max() <= 1e-2 * np.abs(dm).max()
+    dt, dt32 = np.array(dt), np.array(dt32)
+    e_t = np.abs(dt32 - dt).max() / np.abs(dt).max()
+    print(f"[grad32] {lattice} full size T={steps}: J {abs(j32 / j - 1):.2e} dT {e_t:.2e} dtau {abs(du32 / du - 1):.2e} "
+          f"dm {np.abs(dm32 - dm).max() / np.abs(dm).max():.2e} (gate {_tol32(steps):.2e})", flush=True)
+    tol = _tol32(steps)
+    assert abs(j32 / j - 1) <= tol and abs(du32 / du - 1) <= tol and e_t <= tol
+    assert np.abs(dm32 - dm).max() <= tol * np.abs(dm).max()

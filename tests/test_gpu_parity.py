@@ -64,14 +64,17 @@ def test_degenerate_grids_fp64(lattice, shape):
 
 
 # Population blocks hold the largest divisor of ny rows that keeps one direction plane of a
-# block within 8 KiB: these shapes give one row per block (prime ny, wide rows), several
-# blocks per z-plane, and one block per z-plane, so the y-wrap and block crossings are exercised.
-@pytest.mark.parametrize("lattice,storage,shape", [("D3Q19", "f64", (300, 7, 3)),    # 1 row x 7 blocks
-                                                   ("D3Q27", "f32", (96, 48, 3)),    # 16 rows x 3 blocks
-                                                   ("D2Q9", "f64", (130, 33, 1)),    # 3 rows x 11 blocks
-                                                   ("D3Q19", "f32", (24, 20, 6))])   # 20 rows x 1 block
-def test_blocked_layout_shapes(lattice, storage, shape):
+# block within 8 KiB (32 KiB for FP64): these shapes give one row per block (prime ny, wide
+# rows), several blocks per z-plane, and one block per z-plane, so the y-wrap and block
+# crossings are exercised.
+@pytest.mark.parametrize("lattice,storage,shape,rows", [("D3Q19", "f64", (600, 7, 3), 1),   # 1 row x 7 blocks
+                                                        ("D3Q27", "f32", (96, 48, 3), 16),  # 16 rows x 3 blocks
+                                                        ("D2Q9", "f64", (130, 33, 1), 11),  # 11 rows x 3 blocks
+                                                        ("D3Q19", "f32", (24, 20, 6), 20)])  # 20 rows x 1 block
+def test_blocked_layout_shapes(lattice, storage, shape, rows):
     wl = _random_wl(lattice, shape, seed=11)
+    p = lbm.make_params(wl.lattice, storage, wl.shape, wl.tensor, wl.tensor_kind, wl.tau)
+    assert lbm.lbm_rows_per_block(p) == rows
     check(wl, storage, 20)
 
 
@@ -196,6 +199,43 @@ def test_launch_shape_does_not_change_results():
         assert np.array_equal(ref, got), block
 
 
+@pytest.mark.parametrize("lattice,storage,shape,block", [
+    ("D3Q19", "f32", (256, 5, 3), None),     # one work-group per row, four waves
+    ("D3Q19", "f32", (64, 7, 5), None),      # four one-wave rows per work-group, ragged last work-group
+    ("D3Q27", "f16", (128, 3, 4), None),     # two rows per work-group, ragged
+    ("D3Q19", "f64", (192, 4, 3), None),     # three waves per row
+    ("D3Q27", "bf16", (512, 3, 2), None),    # a row spans two work-groups (edges loaded directly)
+    ("D2Q9", "f32", (256, 9, 1), (64, 1)),   # a row spans four one-wave work-groups
+    ("D2Q9", "f64", (128, 10, 1), (64, 2)),  # two rows of two one-wave tiles each
+])
+def test_lane_exchange_pull_is_the_shifted_pull(lattice, storage, shape, block):
+    """Rows of a multiple of 64 cells: the x-shifted pulls load the lane's own x and move one
+    lane across the wave (edge values through LDS or a direct load). Bit for bit the same state
+    as pulling every population with its own shifted load, after collisions too."""
+    wl = _random_wl(lattice, shape, seed=31)
+    bx, by = block if block else (min(256, shape[0]), max(1, 256 // min(256, shape[0])))
+    a = gpu_run(wl, storage, 25, block=(bx, by, 0))
+    b = gpu_run(wl, storage, 25, block=(bx, by, lbm.LBM_LAUNCH_SHIFTED_PULL))
+    assert np.array_equal(a["f"], b["f"])
+    assert a["totals"] == b["totals"]
+
+
+def test_lane_exchange_gray_step_is_the_shifted_pull():
+    """The gray-cell step of the gradient workload (whole 128-cell rows) with both pulls."""
+    shape = (128, 12, 6)
+    rho, s = W.random_fields(shape, 3, 4)
+    gray = np.random.default_rng(4).uniform(0, 0.4, int(np.prod(shape))).astype(np.float32)
+    out = []
+    for flags in (0, lbm.LBM_LAUNCH_SHIFTED_PULL):
+        p = lbm.make_params("D3Q19", "f32", shape, W.random_theta(4), "theta", 0.8, force=[1e-4, 0, 0], gray=True)
+        sim = lbm.Simulation(p, rho, s, mask=gray)
+        sim.set_launch(128, 2, flags)
+        sim.step(30)
+        out.append(sim.f64().cpu().numpy())
+        sim.close()
+    assert np.array_equal(out[0], out[1])
+
+
 @pytest.mark.parametrize("lattice,storage,shape,steps", [("D3Q19", "f64", (256, 6, 4), 40),
                                                          ("D3Q27", "f32", (256, 5, 3), 60),
                                                          ("D2Q9", "f64", (128, 11, 1), 80)])
@@ -205,13 +245,14 @@ def test_row_spanning_tiles_match_oracle(lattice, storage, shape, steps):
     check(wl, storage, steps)
 
 
-@pytest.mark.parametrize("lattice,storage,shape", [("D3Q27", "f32", (24, 20, 18)),   # one block per z-plane
-                                                   ("D3Q19", "f64", (300, 7, 3)),    # one row per block
-                                                   ("D3Q19", "f16", (96, 48, 3))])   # three blocks of 16 rows
-def test_checkpoint_restore_is_exact(lattice, storage, shape):
+@pytest.mark.parametrize("lattice,storage,shape,rows", [("D3Q27", "f32", (24, 20, 18), 20),  # one block per z-plane
+                                                        ("D3Q19", "f64", (600, 7, 3), 1),    # one row per block
+                                                        ("D3Q19", "f16", (128, 96, 3), 32)])  # three blocks of 32 rows
+def test_checkpoint_restore_is_exact(lattice, storage, shape, rows):
     """Export to the canonical [q][N] order and import back through the blocked layout."""
     wl = W.config2(lattice=lattice, shape=shape)
     p = lbm.make_params(wl.lattice, storage, wl.shape, wl.tensor, wl.tensor_kind, wl.tau)
+    assert lbm.lbm_rows_per_block(p) == rows
     a = lbm.Simulation(p, wl.rho, wl.s)
     a.step(13)
     snap = a.get_populations()
@@ -259,6 +300,37 @@ def test_nonfinite_state_is_reported():
     assert ei.value.code == lbm.LBM_ERR_NONFINITE
 
 
+def test_linearly_unstable_parameters_diverge_and_are_reported():
+    """A (tensor, tau) that the linear-stability scan of the oracle's equilibrium flags as
+    unstable (spectral radius > 1 at rest) blows up on the GPU from a small perturbation, and
+    lbm_moments reports it as LBM_ERR_NONFINITE; the same tensor at the scan-stable tau = 0.7
+    stays finite over the same steps."""
+    from oracle import stability as S
+
+    name, n = "D3Q19", 16
+    theta = W.random_theta(2892)
+    ainv = oracle.tensor_to_ainv(theta, "theta", 3)
+    assert S.spectral_radius(name, ainv, 0.55, L=n) > 1.05
+    assert S.spectral_radius(name, ainv, 0.7, L=n) <= 1 + S.STABLE_MARGIN
+    shape = (n, n, n)
+    rho, s = W.random_fields(shape, 3, 9, amp_rho=1e-3, amp_s=1e-3)
+    diverged_at = {}
+    for tau in (0.55, 0.7):
+        p = lbm.make_params(name, "f32", shape, theta, "theta", tau)
+        sim = lbm.Simulation(p, rho, s)
+        for _ in range(40):
+            sim.step(250)
+            try:
+                sim.moments(fields=False)
+            except lbm.LBMError as err:
+                assert err.code == lbm.LBM_ERR_NONFINITE
+                diverged_at[tau] = sim.t
+                break
+        sim.close()
+    print(f"[parity] unstable tau 0.55 reported non-finite at step {diverged_at.get(0.55)}", flush=True)
+    assert 0.55 in diverged_at and 0.7 not in diverged_at
+
+
 def test_stream_copy_kernel():
     a = torch.arange(1 << 20, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
@@ -269,13 +341,17 @@ def test_stream_copy_kernel():
 
 # ---- reduced-precision storage (FP32 arithmetic): error against FP64, stated per field ----------
 
+# measured on MI355X: f16 f 5.3e-5, rho 7.9e-6, s 6.4e-3; bf16 f 3.3e-3, rho 1.1e-4, s 0.42 (BF16's
+# 8-bit significand leaves 2^-9 of the O(0.01) deviations, so the 0.01 shear wave's velocity is
+# resolved only to tens of percent after 1000 steps)
 @pytest.mark.parametrize("storage,shift,bounds", [
-    ("f16", "rest", dict(f=2e-4, rho=1e-4, s=5e-2)),
-    ("bf16", "rest", dict(f=1e-2, rho=1e-3, s=1.0)),
+    ("f16", "rest", dict(f=1.5e-4, rho=2e-5, s=1.6e-2)),
+    ("bf16", "rest", dict(f=8e-3, rho=3e-4, s=1.0)),
 ])
 def test_half_storage_error_is_bounded(storage, shift, bounds):
     """Half-width storage of the shifted deviations: not a parity claim, a measured error
-    budget (config 1 at 1000 steps)."""
+    budget per field (D2Q9 64^2 shear wave, 1000 steps), each bound about 2.5 x the measured
+    error."""
     wl = W.config1()
     g = gpu_run(wl, storage, wl.steps, shift=shift)
     o = oracle_run(wl, wl.steps)
@@ -288,7 +364,8 @@ def test_half_storage_error_is_bounded(storage, shift, bounds):
 
 
 @pytest.mark.parametrize("lattice,shape,storage", [("D3Q19", (13, 7, 5), "f32"), ("D2Q9", (9, 6, 1), "f64"),
-                                                   ("D3Q27", (5, 6, 7), "f16")])
+                                                   ("D3Q27", (5, 6, 7), "f16"), ("D3Q19", (64, 6, 5), "f32"),
+                                                   ("D3Q27", (128, 3, 2), "f64"), ("D2Q9", (512, 3, 1), "bf16")])
 def test_stream_floor_is_free_streaming(lattice, shape, storage):
     """The measurement kernel moves every canonical population along its velocity and nothing
     else: f_i(x) becomes f_i(x - n c_i), bit for bit."""

@@ -103,10 +103,12 @@ def test_porous_reduced_matches_oracle(storage):
     check(wl, storage, 150)
 
 
-@pytest.mark.parametrize("storage,bound", [("f16", 5e-2), ("bf16", 5e-1)])
+# measured on MI355X: f16 f 5.8e-6, rho 4.1e-6, s 2.6e-4; bf16 f 5.2e-5, rho 2.9e-5, s 2.4e-3
+@pytest.mark.parametrize("storage,bound", [("f16", dict(f=1.5e-5, rho=1e-5, s=7e-4)),
+                                           ("bf16", dict(f=1.5e-4, rho=8e-5, s=6e-3))])
 def test_porous_half_storage_error_budget(storage, bound):
-    """Half-width storage on the porous workload: measured error, stated per field (velocity
-    error relative to the oracle's final max |s|)."""
+    """Half-width storage on the porous workload: measured error budget per field (velocity
+    error relative to the oracle's final max |s|), each bound about 2.5 x the measured error."""
     wl = W.config3(n=40)
     wl.meta["force"] = np.array([1e-4, 0.0, 0.0])
     g = gpu_run(wl, storage, 150)
@@ -115,7 +117,8 @@ def test_porous_half_storage_error_budget(storage, bound):
     print(f"[half] porous {storage} {e}", flush=True)
     _log(dict(lattice=wl.lattice, shape=list(wl.shape), storage=storage, order=3, steps=150, reference="oracle",
               case="porous", **{k: float(v) for k, v in e.items()}))
-    assert e["s"] <= bound
+    for k in bound:
+        assert e[k] <= bound[k], (k, e[k])
 
 
 def test_forced_uniform_state_gains_exact_momentum():
