@@ -179,6 +179,19 @@ int lbm_step(lbm_ctx *ctx, int64_t nsteps);
  *           returns LBM_ERR_NONFINITE if any total is NaN or infinite. */
 int lbm_moments(lbm_ctx *ctx, double *rho, double *s, double *totals);
 
+/* lbm_moments for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation). Same arguments, results and errors as
+ * lbm_moments, bit for bit, but the reduction partials and totals live in a static device array
+ * of the library (82,176 bytes, one per device, held until the process ends) instead of the
+ * context's scratch; the call allocates nothing. Every call on a device shares that device's
+ * array: calls that overlap on one device (different streams, or host threads) race and give
+ * wrong totals; calls ordered on one stream do not. With totals == NULL only kernels are
+ * enqueued; with totals the stream is synchronised, as in lbm_moments. Errors: LBM_ERR_ARG,
+ * LBM_ERR_HIP (the array's address could not be looked up on the stream's device), and
+ * LBM_ERR_SIZE if a grid's reduction needed more than the array (not possible for a valid
+ * context: the moments launch never uses more than 2048 work-groups). */
+int lbm_moments_static(lbm_ctx *ctx, double *rho, double *s, double *totals);
+
 /* Canonical pre-collision deviations g_i(t, x) = f_i(t, x) - sigma_i in the storage precision,
  * device [q][N] (lbm_pop_bytes(p) bytes), for checkpointing. Exact (a permutation); solid
  * cells read out as zeros. */

@@ -124,6 +124,7 @@ def _bind(path: str):
         "lbm_step": (ctypes.c_int, [vp, i64]),
         "lbm_stream_floor": (ctypes.c_int, [vp, i64]),
         "lbm_moments": (ctypes.c_int, [vp, vp, vp, dp]),
+        "lbm_moments_static": (ctypes.c_int, [vp, vp, vp, dp]),
         "lbm_get_populations": (ctypes.c_int, [vp, vp]),
         "lbm_set_populations": (ctypes.c_int, [vp, vp]),
         "lbm_get_f64": (ctypes.c_int, [vp, vp]),
@@ -272,6 +273,13 @@ def lbm_stream_floor(ctx: int, nsteps: int) -> None:
 def lbm_moments(ctx: int, rho=None, s=None, want_totals: bool = True):
     tot = (ctypes.c_double * 4)()
     _check(_lib.lbm_moments(ctx, _ptr(rho), _ptr(s), tot if want_totals else None))
+    return list(tot) if want_totals else None
+
+
+def lbm_moments_static(ctx: int, rho=None, s=None, want_totals: bool = True):
+    """lbm_moments with the reduction in the library's static device array (allocates nothing)."""
+    tot = (ctypes.c_double * 4)()
+    _check(_lib.lbm_moments_static(ctx, _ptr(rho), _ptr(s), tot if want_totals else None))
     return list(tot) if want_totals else None
 
 

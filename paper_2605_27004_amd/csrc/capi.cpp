@@ -436,8 +436,16 @@ int lbm_moments(lbm_ctx *c, double *rho, double *s, double *totals)
 {
     if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
     const uint32_t nb = moments_groups(c->grid);
-    double *partials = c->partials;
-    double *dtot = c->partials + kPartials * (size_t)nb;
+    return moments_with(c, rho, s, totals, c->partials, c->partials + kPartials * (size_t)nb);
+}
+
+}  // extern "C"
+
+namespace lbm {
+namespace host {
+
+int moments_with(lbm_ctx *c, double *rho, double *s, double *totals, double *partials, double *dtot)
+{
     hipError_t e = launch_moments(c->p.lattice, c->p.storage, c->grid, c->k64, c->links, c->pop[c->cur], rho, s,
                                   partials, dtot, c->stream);
     if (e != hipSuccess) return fail_hip(e, "moments kernel launch");
@@ -456,6 +464,11 @@ int lbm_moments(lbm_ctx *c, double *rho, double *s, double *totals)
         if (!std::isfinite(totals[m])) return fail(LBM_ERR_NONFINITE, "conservation total %d is not finite", m);
     return LBM_OK;
 }
+
+}  // namespace host
+}  // namespace lbm
+
+extern "C" {
 
 int lbm_get_populations(lbm_ctx *c, void *out)
 {

@@ -82,3 +82,13 @@ struct lbm_ctx {
     int block_x, block_y;
     int launch_flags;
 };
+
+namespace lbm {
+namespace host {
+
+// lbm_moments with the reduction partials (kPartials * moments_groups doubles) and the totals
+// (kPartials doubles) at the given device addresses.
+int moments_with(lbm_ctx *c, double *rho, double *s, double *totals, double *partials, double *dtot);
+
+}  // namespace host
+}  // namespace lbm
