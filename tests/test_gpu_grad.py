@@ -507,8 +507,9 @@ def test_fp32_binary_mask_adjoint_matches_oracle_finite_differences(lattice, sha
 @pytest.mark.parametrize("lattice", ["D2Q9", "D3Q19"])
 def test_gradient_workload_full_size(lattice):
     """The gradient workload at full size (D2Q9 512^2 / D3Q19 128^3 channel with obstacles,
-    2000 steps, checkpoints every 100, outlet flux): the FP64 adjoint against central
-    differences of the FP64 forward with the initial state held fixed, and the FP32 adjoint
+    2000 steps, checkpoints every 100, outlet flux): the FP64 adjoint (tau, every tensor entry,
+    the two largest gray-field derivatives) against central differences of the FP64 forward
+    with the initial state held fixed, and the FP32 adjoint
     (the configured precision) against the FP64 one."""
     wl = W.config4(lattice)
     gray = wl.meta["gray"].astype(np.float32)
@@ -540,11 +541,18 @@ def test_gradient_workload_full_size(lattice):
     h = 1e-4
     fd = (J(tau=wl.tau + h) - J(tau=wl.tau - h)) / (2 * h)
     assert close(du, fd), (du, fd)
+    # every independent tensor entry; an off-diagonal derivative is the one of the symmetric
+    # perturbation T_ab + h, T_ba + h
     h = 1e-5
-    tp = wl.tensor.copy(); tm = wl.tensor.copy()
-    tp[0, 1] += h; tp[1, 0] += h; tm[0, 1] -= h; tm[1, 0] -= h
-    fd = (J(tensor=tp) - J(tensor=tm)) / (2 * h)
-    assert close(dt[0][1], fd), (dt[0][1], fd)
+    d = 2 if lattice == "D2Q9" else 3
+    for a in range(d):
+        for b in range(a, d):
+            tp = wl.tensor.copy(); tm = wl.tensor.copy()
+            tp[a, b] += h; tm[a, b] -= h
+            if a != b:
+                tp[b, a] += h; tm[b, a] -= h
+            fd = (J(tensor=tp) - J(tensor=tm)) / (2 * h)
+            assert close(dt[a][b], fd), (a, b, dt[a][b], fd)
     h = 1e-3
     for cell in np.argsort(-np.abs(dm))[:2]:
         gp = gray.copy(); gm = gray.copy()

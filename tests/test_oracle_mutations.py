@@ -52,6 +52,33 @@ def test_pins_catch_mutant(mutant):
         r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                             os.path.join(ROOT, "tests", "test_oracle_pins.py"),
                             os.path.join(ROOT, "tests", "test_oracle_walls_force.py"),
-                            os.path.join(ROOT, "tests", "test_oracle_gray.py")], cwd=ROOT, env=env,
+                            os.path.join(ROOT, "tests", "test_oracle_gray.py"),
+                            os.path.join(ROOT, "tests", "test_oracle_bruteforce.py")], cwd=ROOT, env=env,
                            capture_output=True, text=True, timeout=600)
         assert r.returncode != 0, f"mutant {mutant} survived the pins:\n{r.stdout[-2000:]}"
+
+
+# mutants of the periodic update, forced or not, that the brute-force transcription alone must
+# catch (tensor forms, walls, gray cells and objectives lie outside what it transcribes)
+BRUTE_FORCE_SCOPE = ["K_sign", "K_transposed_index", "d3q19_weights", "drop_K_in_a3", "force_half_missing_in_readout",
+                     "force_not_divided_by_rho", "h3_sign", "relax_by_tau", "second_order_factor", "stream_backwards",
+                     "third_order_factor", "y_index_swap"]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("mutant", BRUTE_FORCE_SCOPE)
+def test_bruteforce_transcription_alone_catches_mutant(mutant):
+    old, new = MUTANTS[mutant]
+    src = open(SRC).read()
+    with tempfile.TemporaryDirectory() as tmp:
+        c = os.path.join(tmp, "m.c")
+        so = os.path.join(tmp, "m.so")
+        with open(c, "w") as fh:
+            fh.write(src.replace(old, new))
+        subprocess.run(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fopenmp", "-shared", "-fPIC", c, "-o", so,
+                        "-lm"], check=True)
+        env = dict(os.environ, LBM_ORACLE_LIB=so, OMP_NUM_THREADS="2")
+        r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                            os.path.join(ROOT, "tests", "test_oracle_bruteforce.py")], cwd=ROOT, env=env,
+                           capture_output=True, text=True, timeout=600)
+        assert r.returncode != 0, f"mutant {mutant} survived the brute-force transcription:\n{r.stdout[-2000:]}"
