@@ -91,7 +91,11 @@ LEGS = {
     "porous-f32": ("D3Q27 porous medium 512^3, FP32 (links step with body force)", "porous", "f32"),
     "porous-f16": ("D3Q27 porous medium 512^3, FP16-shifted (links step with body force)", "porous", "f16"),
     "adjoint-d3q19": ("gradient workload D3Q19 128^3, FP32: lbm_grad over --steps steps", "adjoint", "f32"),
-    "batched": ("512 batched D3Q19 domains, FP32, step per launch", "batched", "f32"),
+    "batched": ("512 batched D3Q19 domains, FP32, step per launch (domain-major tiles)", "batched", "f32"),
+    "batched-xcd": ("512 batched D3Q19 domains, FP32, step per launch (each domain's tiles on one XCD)", "batched",
+                    "f32"),
+    "batched-persistent": ("512 batched D3Q19 domains, FP32, one cooperative launch (2 work-groups per CU, "
+                           "64 Ki-cell items, XCD placement)", "batched", "f32"),
 }
 
 
@@ -136,6 +140,10 @@ def run_leg(args):
     else:
         wl5 = W.config5()
         bt = lbm.Batch(wl5.lattice, storage, wl5.domains)
+        if args.leg == "batched-persistent":
+            bt.set_schedule(mode="persistent", xcd_group=1, wg_per_cu=2, chunk_cells=65536, group_bytes=0)
+        elif args.leg == "batched-xcd":
+            bt.set_schedule(mode="stepwise", xcd_group=1)
         bt.step(args.warmup)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -143,6 +151,7 @@ def run_leg(args):
         bt.step(args.steps)
         e1.record(bt.stream)
         torch.cuda.synchronize()
+        bt.status()
         rec["us_per_step"] = round(e0.elapsed_time(e1) * 1e3 / args.steps, 2)
         bt.close()
     print(json.dumps(rec), flush=True)
