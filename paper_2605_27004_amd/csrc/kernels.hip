@@ -530,6 +530,44 @@ template <typename C> __device__ inline C m3_at(const NuMoments<C> &m, int a, in
     return m.m3[2 * r + (o > r ? o - 1 : o)];
 }
 
+// The contractions of K with the nu-moments, which do not depend on s: K:M2, (K:M3)_a =
+// K_bc M3_bca and (K M1)_a. With a force the transposed Jacobian is taken at s and at s + F/rho
+// from the same moments, so they are formed once per cell.
+template <typename C> struct KContract {
+    C KM2;
+    C KM3[3];
+    C KM1[3];
+};
+
+template <int D, int ORDER, typename C>
+__device__ inline KContract<C> k_contract(const StepConsts<C> &k, const NuMoments<C> &m)
+{
+    const C Km[3][3] = {{k.k[0], k.k[3], k.k[4]}, {k.k[3], k.k[1], k.k[5]}, {k.k[4], k.k[5], k.k[2]}};
+    const C rc = m.ref * C(1.0 / 3.0);
+    const C M2[3][3] = {{m.m2[0] + rc, m.m2[3], m.m2[4]},
+                        {m.m2[3], m.m2[1] + rc, m.m2[5]},
+                        {m.m2[4], m.m2[5], D == 3 ? m.m2[2] + rc : m.m2[2]}};
+    KContract<C> kc;
+    kc.KM2 = C(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) kc.KM2 = fmad(Km[a][b], M2[a][b], kc.KM2);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        kc.KM3[a] = C(0);
+        kc.KM1[a] = C(0);
+        if constexpr (ORDER == 3) {
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) kc.KM3[a] = fmad(Km[b][c], m3_at(m, b, c, a), kc.KM3[a]);
+            kc.KM1[a] = fmad(Km[a][0], m.m1[0], fmad(Km[a][1], m.m1[1], Km[a][2] * m.m1[2]));
+        }
+    }
+    return kc;
+}
+
 // A0 = d/drho, A_a = d/ds_a (times rho) and the K-sensitivity G of sum_k nu_k f^eq_k(rho, s)
 // for f^eq_k = rho r_k + w_k rho P'_k(s), from the nu-moments. With u = c.s, kc = c.(K s),
 // r = w (1 + 1.5 c.K.c - 0.5 tr K) and P' = 4.5 u^2 - 1.5 |s|^2 + u (A - 4.5 |s|^2 + 4.5 u^2)
@@ -543,11 +581,10 @@ template <typename C> __device__ inline C m3_at(const NuMoments<C> &m, int a, in
 // G + G^T, so G holds the symmetric part (G_ab + G_ba) / 2 as 6 entries xx, yy, zz, xy, xz, yz;
 // add coef * G.
 template <int D, int ORDER, typename C>
-__device__ inline void moment_vjp(const StepConsts<C> &k, const NuMoments<C> &m, C rho, C sx, C sy, C sz, C &A0,
-                                  C &Ax, C &Ay, C &Az, C coef, C *G)
+__device__ inline void moment_vjp(const StepConsts<C> &k, const NuMoments<C> &m, const KContract<C> &kc, C rho, C sx,
+                                  C sy, C sz, C &A0, C &Ax, C &Ay, C &Az, C coef, C *G)
 {
     const C s[3] = {sx, sy, sz};
-    const C Km[3][3] = {{k.k[0], k.k[3], k.k[4]}, {k.k[3], k.k[1], k.k[5]}, {k.k[4], k.k[5], k.k[2]}};
     const C D2[3][3] = {{m.m2[0], m.m2[3], m.m2[4]}, {m.m2[3], m.m2[1], m.m2[5]}, {m.m2[4], m.m2[5], m.m2[2]}};
     const C rc = m.ref * C(1.0 / 3.0);
     const C M2[3][3] = {{D2[0][0] + rc, D2[0][1], D2[0][2]},
@@ -556,14 +593,13 @@ __device__ inline void moment_vjp(const StepConsts<C> &k, const NuMoments<C> &m,
     const C M0 = m.m0 + m.ref;
     const C trK = k.k[0] + k.k[1] + k.k[2];
     const C usq = fmad(sx, sx, fmad(sy, sy, sz * sz));
-    C M2s[3], sM2s = C(0), sM1 = C(0), KM2 = C(0);
+    C M2s[3], sM2s = C(0), sM1 = C(0);
+    const C KM2 = kc.KM2;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         M2s[a] = fmad(M2[a][0], s[0], fmad(M2[a][1], s[1], M2[a][2] * s[2]));
         sM2s = fmad(s[a], M2s[a], sM2s);
         sM1 = fmad(s[a], m.m1[a], sM1);
-#pragma unroll
-        for (int b = 0; b < 3; ++b) KM2 = fmad(Km[a][b], M2[a][b], KM2);
     }
     const C base0 = fmad(C(-0.5) * trK, M0, M0);  // M0 (1 - tr K / 2)
     const C g = C(1.5) * fmad(C(-1), trK, C(2));  // 3 - 1.5 tr K
@@ -574,7 +610,8 @@ __device__ inline void moment_vjp(const StepConsts<C> &k, const NuMoments<C> &m,
     const int ea[6] = {0, 1, 2, 0, 0, 1}, eb[6] = {0, 1, 2, 1, 2, 2};
     const C rcoef = rho * coef;
     if constexpr (ORDER == 3) {
-        C KM3[3], M3ss[3], KM1[3], T3 = C(0), sKM3 = C(0), sKM1 = C(0);
+        const C *KM3 = kc.KM3, *KM1 = kc.KM1;
+        C M3ss[3], T3 = C(0), sKM3 = C(0), sKM1 = C(0);
         C M3s[3][3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -584,15 +621,9 @@ __device__ inline void moment_vjp(const StepConsts<C> &k, const NuMoments<C> &m,
         }
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            KM3[a] = C(0);
-#pragma unroll
-            for (int b = 0; b < 3; ++b)
-#pragma unroll
-                for (int c = 0; c < 3; ++c) KM3[a] = fmad(Km[b][c], m3_at(m, b, c, a), KM3[a]);
             M3ss[a] = fmad(M3s[a][0], s[0], fmad(M3s[a][1], s[1], M3s[a][2] * s[2]));
             T3 = fmad(s[a], M3ss[a], T3);
             sKM3 = fmad(s[a], KM3[a], sKM3);
-            KM1[a] = fmad(Km[a][0], m.m1[0], fmad(Km[a][1], m.m1[1], Km[a][2] * m.m1[2]));
             sKM1 = fmad(s[a], KM1[a], sKM1);
         }
         bracket = fmad(g, sM1, bracket);
@@ -733,7 +764,9 @@ template <int LAT> __device__ inline Slot adjoint_slot_minus(const Cell &c, int 
 
 // One reverse step at one cell: lam_in = lam(t+1) (canonical), state = the buffer whose gather
 // gives f(t); writes lam(t) at the cell, adds d m to dmask and the cell's G / d tau to G, dtau.
-template <int LAT, typename S, int ORDER, bool FORCED>
+// LINKS = false compiles the grid without solid cells (links is null): every slot is then a
+// plain pull and the bounce-back selections drop out of the code.
+template <int LAT, typename S, int ORDER, bool FORCED, bool LINKS>
 __device__ inline void adjoint_cell(const S *__restrict__ state, const typename Conv<S>::C *__restrict__ lam_in,
                                     typename Conv<S>::C *__restrict__ lam_out, const float *__restrict__ gray,
                                     const uint32_t *__restrict__ links, double *__restrict__ dmask, const Grid &g,
@@ -745,8 +778,8 @@ __device__ inline void adjoint_cell(const S *__restrict__ state, const typename 
     constexpr int NP = L::NP;
     const bool inside = x < g.nx && y < g.ny;
     const Cell c = cell_of(g, inside ? x : 0, inside ? y : 0, z);
-    const uint32_t lk = (inside && links) ? links[c.own] : 0u;
-    if (inside && (lk & 1u)) {
+    const uint32_t lk = (LINKS && inside && links) ? links[c.own] : 0u;
+    if (LINKS && inside && (lk & 1u)) {
         // a solid cell holds no state: its adjoint is zero and it adds no sensitivity
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) st_pop(lam_out, g, i, own_ref(c), C(0));
@@ -781,8 +814,9 @@ __device__ inline void adjoint_cell(const S *__restrict__ state, const typename 
         const C a = FORCED ? w - C(1) : w;
         // first pass over the directions: the transposed equilibrium Jacobian (and G)
         const NuMoments<C> nm = nu_moments<LAT>(k, mup, mum, keep);
+        const KContract<C> kcn = k_contract<L::D, ORDER, C>(k, nm);
         C A0, Ax, Ay, Az;
-        moment_vjp<L::D, ORDER, C>(k, nm, rho, sx, sy, sz, A0, Ax, Ay, Az, a, G);
+        moment_vjp<L::D, ORDER, C>(k, nm, kcn, rho, sx, sy, sz, A0, Ax, Ay, Az, a, G);
         C base = a * (A0 - (Ax * sx + Ay * sy + Az * sz) * inv);
         C ax = a * Ax * inv, ay = a * Ay * inv, az = a * Az * inv;
         C tx = C(0), ty = C(0), tz = C(0);
@@ -791,7 +825,7 @@ __device__ inline void adjoint_cell(const S *__restrict__ state, const typename 
             ty = (jy + k.force[1]) * inv;
             tz = (jz + k.force[2]) * inv;
             C B0, Bx, By, Bz;
-            moment_vjp<L::D, ORDER, C>(k, nm, rho, tx, ty, tz, B0, Bx, By, Bz, C(1), G);
+            moment_vjp<L::D, ORDER, C>(k, nm, kcn, rho, tx, ty, tz, B0, Bx, By, Bz, C(1), G);
             base += B0 - (Bx * tx + By * ty + Bz * tz) * inv;
             ax += Bx * inv;
             ay += By * inv;
@@ -840,7 +874,7 @@ __device__ inline void adjoint_cell(const S *__restrict__ state, const typename 
 // [by per, (by + 1) per) of the flattened (y-tile, z) order; each lane accumulates its cells'
 // G / d tau in FP64 and the work-group adds its sums to gpart (in the same order every step,
 // so the totals are reproducible).
-template <int LAT, typename S, int ORDER, bool FORCED>
+template <int LAT, typename S, int ORDER, bool FORCED, bool LINKS>
 __global__ __launch_bounds__(256) void k_adjoint(const S *__restrict__ state, const typename Conv<S>::C *__restrict__ lam_in,
                                                  typename Conv<S>::C *__restrict__ lam_out,
                                                  const float *__restrict__ gray, const uint32_t *__restrict__ links,
@@ -864,7 +898,8 @@ __global__ __launch_bounds__(256) void k_adjoint(const S *__restrict__ state, co
         const int32_t y = (int32_t)((f % tiles_y) * blockDim.y + threadIdx.y);
         C G[6] = {C(0), C(0), C(0), C(0), C(0), C(0)};
         C dtau = C(0);
-        adjoint_cell<LAT, S, ORDER, FORCED>(state, lam_in, lam_out, gray, links, dmask, g, k, x, y, z, G, dtau);
+        adjoint_cell<LAT, S, ORDER, FORCED, LINKS>(state, lam_in, lam_out, gray, links, dmask, g, k, x, y, z, G,
+                                                   dtau);
 #pragma unroll
         for (int e = 0; e < 6; ++e) v[e] += (double)G[e];
         v[6] += (double)dtau;
@@ -1150,14 +1185,19 @@ hipError_t launch_adjoint(int lattice, int storage, int order, const Grid &g, co
             if constexpr (sizeof(C) == 8) kc = &k64; else kc = &k32;
             const dim3 grid = adjoint_grid(g), block = row_block(g);
             const uint32_t per = adjoint_rows_per_group(g);
-#define LBM_ADJ(O, F)                                                                                            \
-    hipLaunchKernelGGL((k_adjoint<LAT, S, O, F>), grid, block, 0, stream, (const S *)state, (const C *)lam_in,     \
+#define LBM_ADJ(O, F, L)                                                                                         \
+    hipLaunchKernelGGL((k_adjoint<LAT, S, O, F, L>), grid, block, 0, stream, (const S *)state, (const C *)lam_in,  \
                        (C *)lam_out, gray, links, dmask, gpart, g, *kc, per)
+#define LBM_ADJ_L(O, F)                                                                                          \
+    do {                                                                                                         \
+        if (links) LBM_ADJ(O, F, true); else LBM_ADJ(O, F, false);                                               \
+    } while (0)
             if (order == 2) {
-                if (kc->forced) LBM_ADJ(2, true); else LBM_ADJ(2, false);
+                if (kc->forced) LBM_ADJ_L(2, true); else LBM_ADJ_L(2, false);
             } else {
-                if (kc->forced) LBM_ADJ(3, true); else LBM_ADJ(3, false);
+                if (kc->forced) LBM_ADJ_L(3, true); else LBM_ADJ_L(3, false);
             }
+#undef LBM_ADJ_L
 #undef LBM_ADJ
             return hipGetLastError();
         });
