@@ -68,26 +68,27 @@ __device__ inline uint32_t tile_of(const TileMap &m, uint32_t b)
 // aid that moves exactly the step's bytes in the step's pattern.
 enum StepMode : int { kPlain = 0, kLinks = 1, kGray = 2, kStream = 3 };
 
-// Pull of a cell's q pre-collision deviations when every wave lies inside one grid row: nx is a
-// multiple of 64 and a work-group spans whole rows or an exact fraction of a row (launch_step
-// checks this). An x-shifted pull would make each wave read three cache lines of which two are
-// shared with the neighbouring waves; measured on the bare D3Q19 256^3 FP32 pattern, that costs
-// 4% of the pass against loading the source row at the lane's own x (every line then read by one
-// wave, non-temporally) and moving the values one lane across the wave with DPP. The one value
-// that crosses a wave's edge comes from the neighbouring wave through LDS, or, at the two ends
-// of a work-group that spans only part of a row, from one wave-uniform load. The result is the
-// same gather, bit for bit. `live` (the wave's row exists) is uniform over each wave; every wave
-// reaches the barrier.
+// Pull of a cell's q pre-collision deviations when every work-group spans whole grid rows: nx
+// is a multiple of 64 and the work-group is nx wide (launch_step checks this). An x-shifted pull
+// would make each wave read three cache lines of which two are shared with the neighbouring
+// waves; measured on the bare D3Q19 256^3 FP32 pattern, that costs 4% of the pass against
+// loading the source row at the lane's own x (every line then read by one wave,
+// non-temporally) and moving the values one lane across the wave with DPP. The one value that
+// crosses a wave's edge comes from the neighbouring wave of the same row through LDS. The
+// result is the same gather, bit for bit. `live` (the wave's row exists) is uniform over each
+// wave; every wave reaches the barrier. Where a row spans several work-groups the end waves'
+// edge values would need loads of their own; measured that way, the exchange lost to shifted
+// loads (D3Q19 FP32 512^3: 3.55 vs 3.40 ms per step; 448^3 in 64-wide work-groups: 2.83 vs
+// 2.24 ms), so such launches use the shifted pull.
 // How the step kernel pulls (launch_step picks): every population with its own shifted load, or
-// the lane exchange of pull_aligned inside whole rows, or inside work-groups that span an exact
-// fraction of a row.
-enum PullKind : int { kPullShifted = 0, kPullRows = 1, kPullRowPart = 2 };
+// the lane exchange of pull_aligned inside whole rows.
+enum PullKind : int { kPullShifted = 0, kPullRows = 1 };
 
 template <int LAT, typename S, int PULL>
 __device__ inline void pull_aligned(const S *__restrict__ src, const Grid &g, const Cell &c, int32_t x, bool live,
                                     typename Conv<S>::C *gp, typename Conv<S>::C *gm)
 {
-    static_assert(PULL == kPullRows || PULL == kPullRowPart, "lane-exchange pulls only");
+    static_assert(PULL == kPullRows, "lane-exchange pulls only");
     using L = Lattice<LAT>;
     using C = typename Conv<S>::C;
     constexpr PullOrder<LAT> kPull{};
@@ -98,10 +99,6 @@ __device__ inline void pull_aligned(const S *__restrict__ src, const Grid &g, co
     const uint32_t wv = threadIdx.y * wpr + pos;
     const uint32_t wl = threadIdx.y * wpr + (pos == 0u ? wpr - 1u : pos - 1u);  // holds x0 - 1 (row wrap)
     const uint32_t wr = threadIdx.y * wpr + (pos == wpr - 1u ? 0u : pos + 1u);  // holds x0 + 64
-    const bool far_l = PULL == kPullRowPart && pos == 0u, far_r = PULL == kPullRowPart && pos == wpr - 1u;
-    const uint32_t x0 = (uint32_t)x - lane;
-    const uint32_t xl = x0 == 0u ? (uint32_t)g.nx - 1u : x0 - 1u;
-    const uint32_t xr = x0 + 64u == (uint32_t)g.nx ? 0u : x0 + 64u;
     if (live) {
 #pragma unroll
         for (int j = 0; j < L::Q; ++j) {
@@ -143,19 +140,10 @@ __device__ inline void pull_aligned(const S *__restrict__ src, const Grid &g, co
         const int cx = sg * v.cx;
         if (cx == 0) continue;
         C &val = (i & 1) ? gp[p + 1] : gm[p + 1];
-        const Ref r = nbr(c, 0, sg * v.cy, sg * v.cz);
-        const uint32_t row0 = r.idx - (uint32_t)x;  // x = 0 of the source row (wave-uniform)
-        if (cx > 0) {  // pulled from x - 1
-            C e = edge[i][wl];
-            if constexpr (PULL == kPullRowPart)
-                if (far_l) e = Conv<S>::ld(ld_at(pop_base(src, g, i, r), row0 + xl));
-            val = wave_shift<kFromLeft>(e, val);
-        } else {       // pulled from x + 1
-            C e = edge[i][wr];
-            if constexpr (PULL == kPullRowPart)
-                if (far_r) e = Conv<S>::ld(ld_at(pop_base(src, g, i, r), row0 + xr));
-            val = wave_shift<kFromRight>(e, val);
-        }
+        if (cx > 0)  // pulled from x - 1
+            val = wave_shift<kFromLeft>(edge[i][wl], val);
+        else         // pulled from x + 1
+            val = wave_shift<kFromRight>(edge[i][wr], val);
     }
 }
 
@@ -1039,23 +1027,17 @@ hipError_t launch_step(int lattice, int storage, int order, const Grid &g, const
             const dim3 grid(m.nblocks);
             const int mode = (flags & kLaunchStreamOnly) ? kStream
                              : gray ? kGray : ((links != nullptr || kc->forced) ? kLinks : kPlain);
-            // the lane-exchange pull needs every wave inside one row (see pull_aligned)
+            // the lane-exchange pull needs work-groups of whole rows (see pull_aligned)
             const bool aligned = mode != kLinks && !(flags & kLaunchShiftedPull) && g.nx % 64 == 0 &&
-                                 g.nx % block_x == 0;
-            const bool whole_rows = block_x == g.nx;
+                                 block_x == g.nx;
             const S *in = (const S *)src;
             S *out = (S *)dst;
 #define LBM_STEP(O, M)                                                                                           \
     do {                                                                                                         \
         if constexpr (M != kLinks) {                                                                             \
-            if (aligned && whole_rows) {                                                                         \
+            if (aligned) {                                                                                       \
                 hipLaunchKernelGGL((k_step<LAT, S, O, M, kPullRows>), grid, block, 0, stream, in, out, g, *kc, m, \
                                    links, gray);                                                                 \
-                break;                                                                                           \
-            }                                                                                                    \
-            if (aligned) {                                                                                       \
-                hipLaunchKernelGGL((k_step<LAT, S, O, M, kPullRowPart>), grid, block, 0, stream, in, out, g, *kc, \
-                                   m, links, gray);                                                              \
                 break;                                                                                           \
             }                                                                                                    \
         }                                                                                                        \

@@ -103,6 +103,55 @@ def test_fp64_export_of_a_grid_beyond_2_29_cells():
     assert abs(got.sum(axis=0) - 1.0).max() < 1e-12
 
 
+def test_step_beyond_2_32_elements_matches_oracle_at_sampled_cells():
+    """One FP32 step of a D3Q19 Taylor-Green state on 1024 x 1024 x 224 cells: each population
+    array holds more than 2^32 elements, so the z-plane offsets of the last planes exceed 32
+    bits. From the equilibrium start the collision leaves f^eq unchanged (up to rounding), so
+    after one step f_i(x) = f^eq_i at x - c_i, and the density and velocity at x follow from the
+    oracle's equilibria of the 19 upstream cells. Checked at cells in the first and last z-planes
+    (periodic wrap), around the 2^32-element boundary and at random."""
+    shape = (1024, 1024, 224)
+    nx, ny, nz = shape
+    n = nx * ny * nz
+    assert n * 19 > 2 ** 32
+    wl = W.config2(shape=shape)
+    ainv = oracle.tensor_to_ainv(wl.tensor, wl.tensor_kind, 3)
+    rng = np.random.default_rng(11)
+    zb = (2 ** 32) // (19 * nx * ny)  # the first z-plane with offsets beyond 2^32 elements
+    zs = [0, 1, zb - 1, zb, zb + 1, nz - 2, nz - 1]
+    cells = [(int(rng.integers(nx)), int(rng.integers(ny)), z) for z in zs for _ in range(40)]
+    cells += [(0, 0, 0), (nx - 1, ny - 1, nz - 1), (nx - 1, 0, zb), (0, ny - 1, nz - 1)]
+    cells += [tuple(int(v) for v in rng.integers([nx, ny, nz])) for _ in range(200)]
+    c = oracle.lattice("D3Q19")[0]
+    want_rho, want_s = [], []
+    for x, y, z in cells:
+        f = np.zeros(19)
+        for i in range(19):
+            xs, ys, zs_ = (x - c[i, 0]) % nx, (y - c[i, 1]) % ny, (z - c[i, 2]) % nz
+            k = (zs_ * ny + ys) * nx + xs
+            f[i] = oracle.feq("D3Q19", ainv, wl.rho[k], wl.s[:, k], 3)[i]
+        r = f.sum()
+        want_rho.append(r)
+        want_s.append((c[:, :3].T @ f) / r)
+    p = lbm.make_params("D3Q19", "f32", shape, wl.tensor, wl.tensor_kind, wl.tau)
+    print(f"[parity] one FP32 step on {shape} ({n * 19} elements per array)", flush=True)
+    sim = lbm.Simulation(p, wl.rho, wl.s)
+    del wl
+    sim.step(1)
+    rho, s, _ = sim.moments()
+    idx = torch.tensor([(z * ny + y) * nx + x for x, y, z in cells], device=rho.device)
+    got_rho = rho[idx].cpu().numpy()
+    got_s = s[:, idx].cpu().numpy().T
+    del rho, s
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    e_rho = np.abs(got_rho - np.array(want_rho)).max()
+    e_s = np.abs(got_s - np.array(want_s)).max() / 0.02
+    print(f"[parity] beyond 2^32 elements: e(rho) {e_rho:.2e}, e(s) {e_s:.2e}", flush=True)
+    assert e_rho < TOL["f32"] and e_s < TOL["f32"]
+
+
 @pytest.mark.parametrize("kind", ["A", "Atilde"])
 def test_tensor_kinds_fp64(kind):
     rng = np.random.default_rng(3)
@@ -204,13 +253,14 @@ def test_launch_shape_does_not_change_results():
     ("D3Q19", "f32", (64, 7, 5), None),      # four one-wave rows per work-group, ragged last work-group
     ("D3Q27", "f16", (128, 3, 4), None),     # two rows per work-group, ragged
     ("D3Q19", "f64", (192, 4, 3), None),     # three waves per row
-    ("D3Q27", "bf16", (512, 3, 2), None),    # a row spans two work-groups (edges loaded directly)
-    ("D2Q9", "f32", (256, 9, 1), (64, 1)),   # a row spans four one-wave work-groups
-    ("D2Q9", "f64", (128, 10, 1), (64, 2)),  # two rows of two one-wave tiles each
+    ("D3Q27", "bf16", (128, 9, 2), None),    # two rows per work-group, BF16
+    ("D2Q9", "f32", (64, 9, 1), (64, 4)),    # one-wave rows, ragged last work-group
+    ("D2Q9", "f64", (128, 10, 1), (128, 2)),  # D2Q9's single z-plane
+    ("D3Q19", "f32", (512, 3, 2), None),     # rows longer than a work-group: shifted pulls either way
 ])
 def test_lane_exchange_pull_is_the_shifted_pull(lattice, storage, shape, block):
-    """Rows of a multiple of 64 cells: the x-shifted pulls load the lane's own x and move one
-    lane across the wave (edge values through LDS or a direct load). Bit for bit the same state
+    """Work-groups of whole rows of a multiple of 64 cells: the x-shifted pulls load the lane's
+    own x and move one lane across the wave (edge values through LDS). Bit for bit the same state
     as pulling every population with its own shifted load, after collisions too."""
     wl = _random_wl(lattice, shape, seed=31)
     bx, by = block if block else (min(256, shape[0]), max(1, 256 // min(256, shape[0])))
