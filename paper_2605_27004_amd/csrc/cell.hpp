@@ -229,6 +229,42 @@ template <typename S> __device__ inline void st_stream(S *p, uint32_t idx, S v)
     __builtin_nontemporal_store(v, reinterpret_cast<S *>(reinterpret_cast<char *>(p) + (uint32_t)(idx * (uint32_t)sizeof(S))));
 }
 
+// Streaming stores of one cell's q populations through a buffer resource based at the cell's
+// z-plane: all q stores share the lane's byte offset and differ by a work-group-uniform offset
+// (direction i at i blocks-per-direction), so they need no per-lane address arithmetic. Offsets
+// stay below 4 GiB because one z-plane of populations does. Cache policy: non-temporal, as
+// st_stream.
+struct PlaneStores {
+    __amdgpu_buffer_rsrc_t rsrc;
+    uint32_t lane_off;    // bytes from the z-plane base to direction 0 of the cell
+    uint32_t plane_step;  // bytes between consecutive direction planes of a block
+};
+
+template <typename S> __device__ inline PlaneStores plane_stores(S *base, const Grid &g, const Ref &r)
+{
+    PlaneStores ps;
+    // raw buffer: stride 0, the largest record count, the data format word of gfx9 raw buffers
+    ps.rsrc = __builtin_amdgcn_make_buffer_rsrc(base + r.zo, (short)0, -1, 0x00020000);
+    ps.lane_off = r.idx * (uint32_t)sizeof(S);
+    ps.plane_step = g.bc * (uint32_t)sizeof(S);
+    return ps;
+}
+
+template <typename S> __device__ inline void st_plane(const PlaneStores &ps, int i, S v)
+{
+    constexpr int kNonTemporal = 2;
+    const int soff = (int)((uint32_t)i * ps.plane_step);
+    if constexpr (sizeof(S) == 2)
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), ps.rsrc, (int)ps.lane_off, soff,
+                                              kNonTemporal);
+    else if constexpr (sizeof(S) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), ps.rsrc, (int)ps.lane_off, soff,
+                                              kNonTemporal);
+    else
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) uint32_t, v),
+                                              ps.rsrc, (int)ps.lane_off, soff, kNonTemporal);
+}
+
 // Non-temporal load of one element (16-bit types go through their bit pattern).
 template <typename S> __device__ inline S ld_nt_at(const S *p, uint32_t idx)
 {

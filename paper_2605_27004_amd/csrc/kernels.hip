@@ -229,11 +229,12 @@ __global__ __launch_bounds__(256) void k_step(const S *__restrict__ src, S *__re
             gm[p + 1] = fmad(mg, pp[p + 1] - gm[p + 1], gm[p + 1]);
         }
     }
-    st_pop_stream(dst, g, 0, own_ref(c), Conv<S>::st(gp[0]));
+    const PlaneStores ps = plane_stores(dst, g, own_ref(c));
+    st_plane(ps, 0, Conv<S>::st(gp[0]));
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-        st_pop_stream(dst, g, 2 * p + 1, own_ref(c), Conv<S>::st(gp[p + 1]));
-        st_pop_stream(dst, g, 2 * p + 2, own_ref(c), Conv<S>::st(gm[p + 1]));
+        st_plane(ps, 2 * p + 1, Conv<S>::st(gp[p + 1]));
+        st_plane(ps, 2 * p + 2, Conv<S>::st(gm[p + 1]));
     }
 }
 
