@@ -58,11 +58,12 @@ __device__ inline void step_cell(const S *__restrict__ src, S *__restrict__ dst,
             gm[p + 1] = Conv<S>::ld(ld_pop(src, g, i, src_minus<LAT>(c, p)));
     }
     collide_cell<LAT, ORDER, false, C, kClose<S>>(k, gp, gm);
-    st_pop_stream(dst, g, 0, own_ref(c), Conv<S>::st(gp[0]));
+    const PlaneStores ps = plane_stores(dst, g, own_ref(c));
+    st_plane(ps, 0, Conv<S>::st(gp[0]));
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-        st_pop_stream(dst, g, 2 * p + 1, own_ref(c), Conv<S>::st(gp[p + 1]));
-        st_pop_stream(dst, g, 2 * p + 2, own_ref(c), Conv<S>::st(gm[p + 1]));
+        st_plane(ps, 2 * p + 1, Conv<S>::st(gp[p + 1]));
+        st_plane(ps, 2 * p + 2, Conv<S>::st(gm[p + 1]));
     }
 }
 

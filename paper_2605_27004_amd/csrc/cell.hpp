@@ -250,20 +250,20 @@ template <typename S> __device__ inline PlaneStores plane_stores(S *base, const 
     return ps;
 }
 
-template <typename S> __device__ inline void st_plane(const PlaneStores &ps, int i, S v)
+// Store of direction i through a PlaneStores; AUX is the cache policy (2: non-temporal, 0: the
+// default, for data read again soon).
+template <int AUX, typename S> __device__ inline void st_plane_aux(const PlaneStores &ps, int i, S v)
 {
-    constexpr int kNonTemporal = 2;
     const int soff = (int)((uint32_t)i * ps.plane_step);
     if constexpr (sizeof(S) == 2)
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), ps.rsrc, (int)ps.lane_off, soff,
-                                              kNonTemporal);
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), ps.rsrc, (int)ps.lane_off, soff, AUX);
     else if constexpr (sizeof(S) == 4)
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), ps.rsrc, (int)ps.lane_off, soff,
-                                              kNonTemporal);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), ps.rsrc, (int)ps.lane_off, soff, AUX);
     else
         __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) uint32_t, v),
-                                              ps.rsrc, (int)ps.lane_off, soff, kNonTemporal);
+                                              ps.rsrc, (int)ps.lane_off, soff, AUX);
 }
+template <typename S> __device__ inline void st_plane(const PlaneStores &ps, int i, S v) { st_plane_aux<2>(ps, i, v); }
 
 // Non-temporal load of one element (16-bit types go through their bit pattern).
 template <typename S> __device__ inline S ld_nt_at(const S *p, uint32_t idx)

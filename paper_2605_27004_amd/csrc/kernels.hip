@@ -768,10 +768,11 @@ __device__ inline void adjoint_cell(const S *__restrict__ state, const typename 
     const bool inside = x < g.nx && y < g.ny;
     const Cell c = cell_of(g, inside ? x : 0, inside ? y : 0, z);
     const uint32_t lk = (LINKS && inside && links) ? links[c.own] : 0u;
+    const PlaneStores out = plane_stores(lam_out, g, own_ref(c));
     if (LINKS && inside && (lk & 1u)) {
         // a solid cell holds no state: its adjoint is zero and it adds no sensitivity
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i) st_pop(lam_out, g, i, own_ref(c), C(0));
+        for (int i = 0; i < L::Q; ++i) st_plane_aux<0>(out, i, C(0));
     } else if (inside) {
         // forward quantities at x (the canonical gather, bounce-back slots included)
         C gp[NP + 1], gm[NP + 1];
@@ -832,7 +833,7 @@ __device__ inline void adjoint_cell(const S *__restrict__ state, const typename 
         // nu_k - nu_0 and mu_k - mu_0 (the rest direction then adds nothing)
         dtau = C(0);
         dm = C(0);
-        st_pop(lam_out, g, 0, own_ref(c), fmad(mg, mup[0], fmad(om, nm.ref, base)));
+        st_plane_aux<0>(out, 0, fmad(mg, mup[0], fmad(om, nm.ref, base)));
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
             C ep, em;
@@ -849,8 +850,8 @@ __device__ inline void adjoint_cell(const S *__restrict__ state, const typename 
             }
             const PairRow v = L::pair(p);
             const C vc = (C)v.cx * ax + (C)v.cy * ay + (C)v.cz * az;
-            st_pop(lam_out, g, 2 * p + 1, own_ref(c), fmad(mg, mum[p + 1], fmad(om, keep * mup[p + 1], base + vc)));
-            st_pop(lam_out, g, 2 * p + 2, own_ref(c), fmad(mg, mup[p + 1], fmad(om, keep * mum[p + 1], base - vc)));
+            st_plane_aux<0>(out, 2 * p + 1, fmad(mg, mum[p + 1], fmad(om, keep * mup[p + 1], base + vc)));
+            st_plane_aux<0>(out, 2 * p + 2, fmad(mg, mup[p + 1], fmad(om, keep * mum[p + 1], base - vc)));
             dm = fmad(mup[p + 1] - mup[0], gm[p + 1] - bp, dm);
             dm = fmad(mum[p + 1] - mup[0], gp[p + 1] - bm, dm);
         }
