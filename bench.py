@@ -157,6 +157,11 @@ def run_leg(args):
     print(json.dumps(rec), flush=True)
 
 
+def progress(msg):
+    """One progress line on stderr after each block (the JSON result stays alone on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_sha():
     h = hashlib.sha256()
     for path in KERNEL_SRCS:
@@ -307,6 +312,7 @@ def main():
                    "run_ms_per_step": None if run_secs is None else [round(t / args.steps * 1e3, 5) for t in run_secs]},
     }
 
+    progress(f"headline done: {kernel_s * 1e6:.1f} us per step")
     # ---- storage variants: speed and error against the FP64 path at full size ----
     if not args.no_variants:
         def run_fields(storage, steps):
@@ -347,6 +353,7 @@ def main():
         del got, ref
         torch.cuda.empty_cache()
         line["variants"] = variants
+        progress("storage variants done")
     # ---- gradient workload: adjoint/forward time ratio ----
     if not args.no_adjoint:
         adj = {}
@@ -372,6 +379,7 @@ def main():
             torch.cuda.empty_cache()
         line["adjoint"] = adj
         line["adjoint_fwd_ratio"] = adj["D3Q19"]["ratio_total"]
+        progress("gradient workload done")
     else:
         line["adjoint_fwd_ratio"] = None
 
@@ -410,6 +418,7 @@ def main():
         del ref3, mask
         torch.cuda.empty_cache()
         line["porous"] = por
+        progress("porous medium done")
 
     # ---- batched small domains: one schedule picked by the autotuner ----
     if not args.no_batched:
@@ -454,6 +463,7 @@ def main():
         del bt
         torch.cuda.empty_cache()
         line["batched"] = res
+        progress("batched domains done")
 
     # ---- CPU baseline: the FP64 oracle on a bounded sample of the same workload ----
     if not args.no_cpu_baseline:
