@@ -209,11 +209,15 @@ int lbm_get_f64(lbm_ctx *ctx, double *out);
 int64_t lbm_time(const lbm_ctx *ctx);
 
 /* Step-kernel launch options: work-group shape block_x * block_y cells (block_x a multiple of
- * 64, block_x * block_y <= 256; the default spans whole x rows up to 256 cells) and flags. */
+ * 64, block_x * block_y <= 256) and flags. The default spans whole x rows up to 256 cells
+ * (block_y = 256 / block_x rows); longer rows take the width of 256, 128 or 64 cells that pads
+ * the row least, the widest on a tie. */
 #define LBM_LAUNCH_XCD_SLABS 1    /* hand each of the 8 XCDs one contiguous slab of tiles */
 #define LBM_LAUNCH_SHIFTED_PULL 2 /* pull every population with its own shifted load. By default, when
-                                     nx is a multiple of 64 and of block_x, x-shifted pulls load the
-                                     lane's own x and move the values one lane across the wave. */
+                                     nx is a multiple of 64 and block_x == nx (work-groups of whole
+                                     rows), x-shifted pulls load the lane's own x and move the values
+                                     one lane across the wave; other launches always use shifted
+                                     loads. */
 
 /* Override the step kernel's launch. Results do not depend on it: every cell is computed by
  * the same arithmetic whatever work-group computes it. */
