@@ -241,6 +241,10 @@ def main():
         p = lbm.make_params(wl.lattice, storage, wl.shape, wl.tensor, wl.tensor_kind, wl.tau, order)
         return lbm.Simulation(p, wl.rho, wl.s)
 
+    # the headline context first: its set-up (fields from the host, init kernel) leaves the GPU
+    # idle for a while, so the copy-kernel calibration below runs between it and the timed steps
+    sim = make("f32")
+
     # ---- plain copy kernel over the same bytes (practical ceiling; also brings the clocks up) ----
     nbytes = q * 4 * cells
     src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
@@ -261,7 +265,6 @@ def main():
     torch.cuda.empty_cache()
 
     # ---- headline: FP32 storage, median of --runs timed runs of exactly --steps steps ----
-    sim = make("f32")
     runs = max(1, args.runs)
     if runs > 1:
         secs, run_secs = timed_steps(sim, args.steps, args.warmup, torch, runs=runs)
