@@ -367,7 +367,7 @@ def main():
                                  gray=True)
             sim4 = lbm.Simulation(p4, wl4.rho, wl4.s, mask=gray)
             sim4.grad("flux", 20, 10, wl4.meta["outlet_plane"], want_dmask=True)   # warm-up
-            t_fwd = timed_steps(sim4, wl4.steps, 0, torch)
+            t_fwd = timed_steps(sim4, wl4.steps, 100, torch)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             jv, _, _, _ = sim4.grad("flux", wl4.steps, wl4.meta["checkpoint_every"], wl4.meta["outlet_plane"])

@@ -223,15 +223,6 @@ int64_t lbm_time(const lbm_ctx *ctx);
  * the same arithmetic whatever work-group computes it. */
 int lbm_set_launch(lbm_ctx *ctx, int32_t block_x, int32_t block_y, int32_t flags);
 
-/* 1 if lbm_step runs this context's steps through HIP graphs, 0 if it launches each step, or
- * LBM_ERR_ARG. Grids whose population array holds at most 64 MiB (steps of a few tens of
- * microseconds or less, where launch overhead dominates) replay a graph of 32 step launches for
- * every whole block of 32 steps and launch the remainder directly; the graphs are built on first
- * use (one per parity of the current buffer) on a stream of the context's own, hold kernel
- * launches only, are rebuilt after lbm_set_launch and are released by lbm_destroy. The results
- * are those of launching each step. */
-int lbm_uses_step_graphs(const lbm_ctx *ctx);
-
 /* Gradients by the discrete adjoint of the step (reverse sweep with checkpointing).
  *
  * lbm_grad advances the context by spec->nsteps steps (exactly as lbm_step would), evaluates

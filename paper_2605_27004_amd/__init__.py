@@ -130,7 +130,6 @@ def _bind(path: str):
         "lbm_get_f64": (ctypes.c_int, [vp, vp]),
         "lbm_time": (i64, [vp]),
         "lbm_set_launch": (ctypes.c_int, [vp, i32, i32, i32]),
-        "lbm_uses_step_graphs": (ctypes.c_int, [vp]),
         "lbm_grad_workspace_bytes": (i64, [vp, ctypes.POINTER(lbm_grad_spec)]),
         "lbm_grad": (ctypes.c_int, [vp, ctypes.POINTER(lbm_grad_spec), vp, dp, dp, dp, vp]),
         "lbm_objective": (ctypes.c_int, [vp, i32, i64, dp]),
@@ -302,13 +301,6 @@ def lbm_time(ctx: int) -> int:
 
 def lbm_set_launch(ctx: int, block_x: int, block_y: int, flags: int = 0) -> None:
     _check(_lib.lbm_set_launch(ctx, int(block_x), int(block_y), int(flags)))
-
-
-def lbm_uses_step_graphs(ctx: int) -> bool:
-    """Whether lbm_step replays HIP graphs of step launches for this context."""
-    rc = _lib.lbm_uses_step_graphs(ctx)
-    _check(min(rc, 0))
-    return rc == 1
 
 
 def make_grad_spec(objective="kinetic_energy", nsteps=0, checkpoint_every=100, outlet_plane=0) -> lbm_grad_spec:

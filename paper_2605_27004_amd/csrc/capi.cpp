@@ -301,77 +301,6 @@ template StepConsts<double> consts_for<double>(const lbm_params &, const Prepare
 
 using namespace lbm::host;
 
-namespace {
-
-// Step graphs: launch overhead dominates the step of a small grid (a D2Q9 64^2 step runs in a
-// few microseconds), so lbm_step replays a captured graph of kGraphSteps launches there. Large
-// grids launch directly: their steps are hundreds of microseconds long.
-constexpr int64_t kGraphSteps = 32;
-constexpr int64_t kGraphMaxPopBytes = 64ll << 20;
-
-bool uses_graphs(const lbm_ctx *c)
-{
-    return (int64_t)c->pr.n * c->pr.q * c->pr.bytes <= kGraphMaxPopBytes;
-}
-
-void drop_graphs(lbm_ctx *c)
-{
-    for (hipGraphExec_t &g : c->graph)
-        if (g) {
-            (void)hipGraphExecDestroy(g);
-            g = nullptr;
-        }
-}
-
-// The executable graph of kGraphSteps steps from the current buffer, built on first use: the
-// launches are captured on the context's own capture stream (so the caller's stream may be the
-// null stream) and replayed on the context's stream. The graph holds kernel launches only.
-int step_graph(lbm_ctx *c, hipGraphExec_t *out)
-{
-    if (c->graph_bx != c->block_x || c->graph_by != c->block_y || c->graph_flags != c->launch_flags) {
-        drop_graphs(c);
-        c->graph_bx = c->block_x;
-        c->graph_by = c->block_y;
-        c->graph_flags = c->launch_flags;
-    }
-    hipGraphExec_t &g = c->graph[c->cur];
-    if (!g) {
-        hipError_t e = hipSuccess;
-        if (!c->capture) e = hipStreamCreateWithFlags(&c->capture, hipStreamNonBlocking);
-        if (e != hipSuccess) return fail_hip(e, "capture stream");
-        e = hipStreamBeginCapture(c->capture, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess) return fail_hip(e, "begin step graph capture");
-        hipError_t le = hipSuccess;
-        for (int64_t s = 0; s < kGraphSteps && le == hipSuccess; ++s) {
-            const int from = c->cur ^ (int)(s & 1);
-            le = launch_step(c->p.lattice, c->p.storage, c->p.order, c->grid, c->k64, c->k32, c->links, c->gray,
-                             c->pop[from], c->pop[from ^ 1], c->block_x, c->block_y, c->launch_flags, c->capture);
-        }
-        hipGraph_t graph = nullptr;
-        e = hipStreamEndCapture(c->capture, &graph);
-        if (le != hipSuccess || e != hipSuccess) {
-            if (graph) (void)hipGraphDestroy(graph);
-            return fail_hip(le != hipSuccess ? le : e, "step graph capture");
-        }
-        e = hipGraphInstantiate(&g, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        if (e != hipSuccess) {
-            g = nullptr;
-            return fail_hip(e, "step graph instantiation");
-        }
-    }
-    *out = g;
-    return LBM_OK;
-}
-
-}  // namespace
-
-lbm_ctx::~lbm_ctx()
-{
-    drop_graphs(this);
-    if (capture) (void)hipStreamDestroy(capture);
-}
-
 extern "C" {
 
 int lbm_lattice_info(int32_t lattice, int32_t *q, int32_t *d, int32_t *c, double *w, int32_t *opp)
@@ -506,18 +435,6 @@ int lbm_step(lbm_ctx *c, int64_t nsteps)
 {
     if (!c) return fail(LBM_ERR_ARG, "ctx is NULL");
     if (nsteps < 0) return fail(LBM_ERR_ARG, "nsteps must be >= 0");
-    if (uses_graphs(c)) {
-        // whole blocks of kGraphSteps steps replay one graph; kGraphSteps is even, so the
-        // current buffer is the same after each block
-        for (; nsteps >= kGraphSteps; nsteps -= kGraphSteps) {
-            hipGraphExec_t g = nullptr;
-            const int rc = step_graph(c, &g);
-            if (rc) return rc;
-            const hipError_t e = hipGraphLaunch(g, c->stream);
-            if (e != hipSuccess) return fail_hip(e, "step graph launch");
-            c->t += kGraphSteps;
-        }
-    }
     for (int64_t s = 0; s < nsteps; ++s) {
         hipError_t e = launch_step(c->p.lattice, c->p.storage, c->p.order, c->grid, c->k64, c->k32, c->links,
                                    c->gray, c->pop[c->cur], c->pop[c->cur ^ 1], c->block_x, c->block_y,
@@ -785,8 +702,6 @@ int lbm_objective(lbm_ctx *c, int32_t objective, int64_t outlet_plane, double *v
 }
 
 void lbm_destroy(lbm_ctx *c) { delete c; }
-
-int lbm_uses_step_graphs(const lbm_ctx *c) { return c ? (uses_graphs(c) ? 1 : 0) : fail(LBM_ERR_ARG, "ctx is NULL"); }
 
 const char *lbm_last_error(void) { return g_last_error.c_str(); }
 

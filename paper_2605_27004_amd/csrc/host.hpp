@@ -81,13 +81,6 @@ struct lbm_ctx {
     int64_t t;
     int block_x, block_y;
     int launch_flags;
-    // Small grids step through a HIP graph of kGraphSteps launches, one executable per parity
-    // of the current buffer, built on first use by capturing the launches on a stream of the
-    // context's own and rebuilt after lbm_set_launch.
-    hipStream_t capture = nullptr;
-    hipGraphExec_t graph[2] = {nullptr, nullptr};
-    int graph_bx = 0, graph_by = 0, graph_flags = -1;
-    ~lbm_ctx();
 };
 
 namespace lbm {

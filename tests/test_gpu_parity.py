@@ -270,55 +270,6 @@ def test_lane_exchange_pull_is_the_shifted_pull(lattice, storage, shape, block):
     assert a["totals"] == b["totals"]
 
 
-@pytest.mark.parametrize("lattice,storage,shape", [("D2Q9", "f64", (64, 64, 1)), ("D3Q19", "f32", (24, 20, 18)),
-                                                   ("D3Q27", "f16", (16, 12, 10))])
-def test_step_graphs_match_direct_launches(lattice, storage, shape):
-    """Small grids step through replayed HIP graphs of 32 launches. The state matches stepping
-    one launch at a time, bit for bit: through both parities of the buffer pair, across replays
-    with other work (read-outs) on the stream in between, and after lbm_set_launch has made the
-    graphs be rebuilt."""
-    wl = _random_wl(lattice, shape, seed=41)
-    p = lbm.make_params(lattice, storage, shape, wl.tensor, wl.tensor_kind, wl.tau)
-    a = lbm.Simulation(p, wl.rho, wl.s)
-    b = lbm.Simulation(p, wl.rho, wl.s)
-    assert lbm.lbm_uses_step_graphs(a.ctx)
-
-    def compare(tag):
-        _, _, ta = a.moments()
-        _, _, tb = b.moments()
-        assert ta == tb, tag
-        assert torch.equal(a.f64(), b.f64()), tag
-
-    # 64: two replays; 1: direct (the parity flips); 32: the other parity's graph; 7: direct;
-    # 96: three replays
-    for n in (64, 1, 32, 7, 96):
-        a.step(n)
-        for _ in range(n):
-            b.step(1)
-        compare(n)
-    bx = 64
-    a.set_launch(bx, 4, lbm.LBM_LAUNCH_SHIFTED_PULL)
-    b.set_launch(bx, 4, lbm.LBM_LAUNCH_SHIFTED_PULL)
-    a.step(65)
-    for _ in range(65):
-        b.step(1)
-    compare("after set_launch")
-    assert lbm.lbm_time(a.ctx) == lbm.lbm_time(b.ctx) == 64 + 1 + 32 + 7 + 96 + 65
-    a.close()
-    b.close()
-
-
-def test_large_grids_launch_each_step():
-    """A grid whose population array exceeds 64 MiB launches each step directly."""
-    shape = (128, 128, 64)
-    rho, s = W.uniform_fields(shape, 3)
-    p = lbm.make_params("D3Q19", "f32", shape, W.config2_theta(0), "theta", 0.7)
-    assert lbm.lbm_pop_bytes(p) > 64 << 20
-    sim = lbm.Simulation(p, rho, s)
-    assert not lbm.lbm_uses_step_graphs(sim.ctx)
-    sim.close()
-
-
 def test_lane_exchange_gray_step_is_the_shifted_pull():
     """The gray-cell step of the gradient workload (whole 128-cell rows) with both pulls."""
     shape = (128, 12, 6)
