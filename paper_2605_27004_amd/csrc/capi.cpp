@@ -255,6 +255,7 @@ template <typename C> StepConsts<C> consts_for(const lbm_params &p, const Prepar
     std::memset(&k, 0, sizeof k);
     const lbm_derived &dv = pr.dv;
     k.omega = (C)dv.omega;
+    k.keep = (C)(1.0 - dv.omega);
     k.rho0 = (C)p.rho0;
     k.k[0] = (C)dv.k[0];
     k.k[1] = (C)dv.k[4];
@@ -262,6 +263,8 @@ template <typename C> StepConsts<C> consts_for(const lbm_params &p, const Prepar
     k.k[3] = (C)dv.k[1];
     k.k[4] = (C)dv.k[2];
     k.k[5] = (C)dv.k[5];
+    const int kidx[6] = {0, 4, 8, 1, 2, 5};
+    for (int e = 0; e < 6; ++e) k.km3[e] = (C)(-3.0 * dv.k[kidx[e]]);
     const double trk = dv.k[0] + dv.k[4] + dv.k[8];
     for (int pp = 0; pp <= pr.lat.np; ++pp) {
         const int i = pp == 0 ? 0 : 2 * pp - 1;  // the + member of pair pp (or the rest)
@@ -271,6 +274,9 @@ template <typename C> StepConsts<C> consts_for(const lbm_params &p, const Prepar
         k.w[pp] = (C)pr.lat.w[i];
         k.rest[pp] = (C)dv.rest[i];
         k.eoff[pp] = (C)(p.rho0 * dv.rest[i] - dv.shift[i]);
+        k.ow[pp] = (C)(dv.omega * pr.lat.w[i]);
+        k.orest[pp] = (C)(dv.omega * dv.rest[i]);
+        k.oeoff[pp] = (C)(dv.omega * (p.rho0 * dv.rest[i] - dv.shift[i]));
         k.a[pp] = (C)(3.0 + 4.5 * ckc - 1.5 * trk);
         k.sigma[pp] = (C)dv.shift[i];
     }

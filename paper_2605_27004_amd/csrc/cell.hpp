@@ -333,7 +333,7 @@ template <int LAT> struct PullOrder {
 
 // Per-cell quantities of the folded equilibrium that every velocity pair shares.
 template <typename C> struct EqCell {
-    C rho, drho, sx, sy, sz, ksx, ksy, ksz, even0, bq;
+    C rho, drho, sx, sy, sz, k3x, k3y, k3z, even0, bq;  // k3 = -3 K s
 };
 
 template <typename C>
@@ -346,12 +346,22 @@ __device__ inline EqCell<C> eq_cell(const StepConsts<C> &k, C drho, C rho, C sx,
     e.sy = sy;
     e.sz = sz;
     const C usq = fmad(sx, sx, fmad(sy, sy, sz * sz));
-    e.ksx = fmad(k.k[0], sx, fmad(k.k[3], sy, k.k[4] * sz));
-    e.ksy = fmad(k.k[3], sx, fmad(k.k[1], sy, k.k[5] * sz));
-    e.ksz = fmad(k.k[4], sx, fmad(k.k[5], sy, k.k[2] * sz));
+    e.k3x = fmad(k.km3[0], sx, fmad(k.km3[3], sy, k.km3[4] * sz));
+    e.k3y = fmad(k.km3[3], sx, fmad(k.km3[1], sy, k.km3[5] * sz));
+    e.k3z = fmad(k.km3[4], sx, fmad(k.km3[5], sy, k.km3[2] * sz));
     e.even0 = C(-1.5) * usq;
     e.bq = C(-4.5) * usq;
     return e;
+}
+
+// c . (ax, ay, az) for c in {-1, 0, 1}^3 (c != 0), summed in x, y, z order from the first
+// non-zero term: no leading 0 + term, which IEEE arithmetic keeps as an instruction.
+template <typename C> __device__ inline C c_dot(int cx, int cy, int cz, C ax, C ay, C az)
+{
+    C r = cx != 0 ? (cx > 0 ? ax : -ax) : (cy != 0 ? (cy > 0 ? ay : -ay) : (cz > 0 ? az : -az));
+    if (cx != 0 && cy != 0) r = cy > 0 ? r + ay : r - ay;
+    if ((cx != 0 || cy != 0) && cz != 0) r = cz > 0 ? r + az : r - az;
+    return r;
 }
 
 // g^eq of the rest velocity.
@@ -360,27 +370,29 @@ template <typename C> __device__ inline C eq_rest(const StepConsts<C> &k, const 
     return fmad(k.w[0] * e.rho, e.even0, fmad(k.rest[0], e.drho, k.eoff[0]));
 }
 
+// Even and odd s-dependent parts of pair p's equilibrium: g^eq(+-c) = w rho (even +- odd) + base.
+template <int LAT, int ORDER, typename C>
+__device__ inline void eq_parts(const StepConsts<C> &k, const EqCell<C> &e, int p, C &even, C &odd)
+{
+    const PairRow v = Lattice<LAT>::pair(p);
+    // u = c.s and -3 kc = c.(-3 K s) for c in {-1, 0, 1}^3
+    const C u = c_dot(v.cx, v.cy, v.cz, e.sx, e.sy, e.sz);
+    const C u2 = u * u;
+    even = fmad(C(4.5), u2, e.even0);
+    if constexpr (ORDER == 3) {
+        const C k3c = c_dot(v.cx, v.cy, v.cz, e.k3x, e.k3y, e.k3z);
+        odd = fmad(u, fmad(C(4.5), u2, k.a[p + 1] + e.bq), k3c);
+    } else {
+        odd = C(3) * u;
+    }
+}
+
 // g^eq of the +c / -c members of pair p.
 template <int LAT, int ORDER, typename C>
 __device__ inline void eq_pair(const StepConsts<C> &k, const EqCell<C> &e, int p, C &ep, C &em)
 {
-    const PairRow v = Lattice<LAT>::pair(p);
-    // u = c.s and kc = c.(K s) for c in {-1, 0, 1}^3
-    C u = C(0), kc = C(0);
-    if (v.cx > 0) { u += e.sx; kc += e.ksx; }
-    if (v.cx < 0) { u -= e.sx; kc -= e.ksx; }
-    if (v.cy > 0) { u += e.sy; kc += e.ksy; }
-    if (v.cy < 0) { u -= e.sy; kc -= e.ksy; }
-    if (v.cz > 0) { u += e.sz; kc += e.ksz; }
-    if (v.cz < 0) { u -= e.sz; kc -= e.ksz; }
-    const C u2 = u * u;
-    const C even = fmad(C(4.5), u2, e.even0);
-    C odd;
-    if constexpr (ORDER == 3) {
-        odd = fmad(u, fmad(C(4.5), u2, k.a[p + 1] + e.bq), C(-3) * kc);
-    } else {
-        odd = C(3) * u;
-    }
+    C even, odd;
+    eq_parts<LAT, ORDER, C>(k, e, p, even, odd);
     const C wr = k.w[p + 1] * e.rho;
     const C base = fmad(k.rest[p + 1], e.drho, k.eoff[p + 1]);
     ep = fmad(wr, even + odd, base);
@@ -399,24 +411,40 @@ __device__ inline void equilibrium_pairs(const StepConsts<C> &k, C drho, C rho, 
     for (int p = 0; p < Lattice<LAT>::NP; ++p) eq_pair<LAT, ORDER, C>(k, e, p, eqp[p + 1], eqm[p + 1]);
 }
 
+// BGK relaxation g* = g + omega (g^eq - g) written as (1 - omega) g + omega g^eq, with
+// omega g^eq assembled from constants that carry the factor omega (the equilibrium's own
+// constants times omega): one operation per direction fewer than forming g^eq first.
+template <int LAT, int ORDER, typename C>
+__device__ inline void relax_pairs(const StepConsts<C> &k, C drho, C rho, C sx, C sy, C sz, C *gp, C *gm)
+{
+    const EqCell<C> e = eq_cell(k, drho, rho, sx, sy, sz);
+    gp[0] = fmad(k.keep, gp[0], fmad(k.ow[0] * e.rho, e.even0, fmad(k.orest[0], e.drho, k.oeoff[0])));
+#pragma unroll
+    for (int p = 0; p < Lattice<LAT>::NP; ++p) {
+        C even, odd;
+        eq_parts<LAT, ORDER, C>(k, e, p, even, odd);
+        const C owr = k.ow[p + 1] * e.rho;
+        const C obase = fmad(k.orest[p + 1], e.drho, k.oeoff[p + 1]);
+        gp[p + 1] = fmad(k.keep, gp[p + 1], fmad(owr, even + odd, obase));
+        gm[p + 1] = fmad(k.keep, gm[p + 1], fmad(owr, even - odd, obase));
+    }
+}
+
 template <int LAT, typename C> __device__ inline void moments_of(const C *gp, const C *gm, C &drho, C &jx, C &jy, C &jz)
 {
     using L = Lattice<LAT>;
     drho = gp[0];
-    jx = C(0);
-    jy = C(0);
-    jz = C(0);
+    // each momentum component starts from its first contribution (no leading 0 + term)
+    bool bx = false, by = false, bz = false;
+    jx = jy = jz = C(0);
 #pragma unroll
     for (int p = 0; p < L::NP; ++p) {
         const PairRow v = L::pair(p);
         drho += gp[p + 1] + gm[p + 1];
         const C dif = gp[p + 1] - gm[p + 1];
-        if (v.cx > 0) jx += dif;
-        if (v.cx < 0) jx -= dif;
-        if (v.cy > 0) jy += dif;
-        if (v.cy < 0) jy -= dif;
-        if (v.cz > 0) jz += dif;
-        if (v.cz < 0) jz -= dif;
+        if (v.cx != 0) jx = bx ? (v.cx > 0 ? jx + dif : jx - dif) : (v.cx > 0 ? dif : -dif), bx = true;
+        if (v.cy != 0) jy = by ? (v.cy > 0 ? jy + dif : jy - dif) : (v.cy > 0 ? dif : -dif), by = true;
+        if (v.cz != 0) jz = bz ? (v.cz > 0 ? jz + dif : jz - dif) : (v.cz > 0 ? dif : -dif), bz = true;
     }
 }
 
@@ -480,6 +508,13 @@ __device__ inline void collide_cell(const StepConsts<C> &k, C *gp, C *gm)
     moments_of<LAT>(gp, gm, drho, jx, jy, jz);
     const C rho = k.rho0 + drho;
     const C inv = C(1) / rho;
+    if constexpr (!CLOSE) {
+        // without the closure g^eq itself is not needed: relax against omega g^eq directly
+        if (!FORCE || !k.forced) {
+            relax_pairs<LAT, ORDER, C>(k, drho, rho, jx * inv, jy * inv, jz * inv, gp, gm);
+            return;
+        }
+    }
     C eqp[NP + 1], eqm[NP + 1];
     equilibrium_pairs<LAT, ORDER, C>(k, drho, rho, jx * inv, jy * inv, jz * inv, eqp, eqm);
     if constexpr (CLOSE) close_moments<LAT>(eqp, eqm, drho, jx, jy, jz);

@@ -24,11 +24,16 @@ enum StorageId : int { kF64 = 0, kF32 = 1, kF16 = 2, kBF16 = 3 };
 //     g^eq = r (rho - rho0) + (rho0 r - sigma) + w rho P'(s).
 template <typename C> struct StepConsts {
     C omega;            // 1 / tau
+    C keep;             // 1 - omega
     C rho0;             // reference density of the shift
     C k[6];             // K_xx, K_yy, K_zz, K_xy, K_xz, K_yz
+    C km3[6];           // -3 K, the same entries (the odd part's K s term)
     C w[kMaxPairs + 1];     // weight w_p
     C rest[kMaxPairs + 1];  // r_p
     C eoff[kMaxPairs + 1];  // rho0 r_p - sigma_p (zero for the rest-equilibrium shift)
+    C ow[kMaxPairs + 1];    // omega w_p     (omega g^eq, the relaxed equilibrium)
+    C orest[kMaxPairs + 1]; // omega r_p
+    C oeoff[kMaxPairs + 1]; // omega (rho0 r_p - sigma_p)
     C a[kMaxPairs + 1];     // A_p of the odd part (order 3)
     C sigma[kMaxPairs + 1]; // sigma_p (read-out only)
     C force[3];             // body force F (exact-difference method)
