@@ -508,12 +508,12 @@ __device__ inline void collide_cell(const StepConsts<C> &k, C *gp, C *gm)
     moments_of<LAT>(gp, gm, drho, jx, jy, jz);
     const C rho = k.rho0 + drho;
     const C inv = C(1) / rho;
-    if constexpr (!CLOSE) {
-        // without the closure g^eq itself is not needed: relax against omega g^eq directly
-        if (!FORCE || !k.forced) {
-            relax_pairs<LAT, ORDER, C>(k, drho, rho, jx * inv, jy * inv, jz * inv, gp, gm);
-            return;
-        }
+    if constexpr (!CLOSE && !FORCE) {
+        // without the closure g^eq itself is not needed: relax against omega g^eq directly.
+        // (Kernels with the force keep one relaxation form: a second one, with its own set of
+        // constants, took the D3Q27 FP64 masked step from 208 to 255 VGPRs.)
+        relax_pairs<LAT, ORDER, C>(k, drho, rho, jx * inv, jy * inv, jz * inv, gp, gm);
+        return;
     }
     C eqp[NP + 1], eqm[NP + 1];
     equilibrium_pairs<LAT, ORDER, C>(k, drho, rho, jx * inv, jy * inv, jz * inv, eqp, eqm);
