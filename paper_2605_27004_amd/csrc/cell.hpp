@@ -430,6 +430,34 @@ __device__ inline void relax_pairs(const StepConsts<C> &k, C drho, C rho, C sx, 
     }
 }
 
+// BGK with the exact-difference force, g* = (1 - omega) (g - g^eq(s)) + g^eq(s + F/rho), for
+// kernels without the closure. The two equilibria share w rho and the constant part, so with
+// E, O the even and odd parts at s and E', O' at s + F/rho each pair member is
+// g*+- = (1 - omega) g+- + w rho [(E' - (1 - omega) E) +- (O' - (1 - omega) O)] + omega base:
+// the pair's two differences are formed once and neither equilibrium is assembled.
+template <int LAT, int ORDER, typename C>
+__device__ inline void relax_forced_pairs(const StepConsts<C> &k, C drho, C rho, C inv, C jx, C jy, C jz, C *gp,
+                                          C *gm)
+{
+    const EqCell<C> e = eq_cell(k, drho, rho, jx * inv, jy * inv, jz * inv);
+    const EqCell<C> f = eq_cell(k, drho, rho, (jx + k.force[0]) * inv, (jy + k.force[1]) * inv,
+                                (jz + k.force[2]) * inv);
+    const C keep = k.keep;
+    gp[0] = fmad(keep, gp[0],
+                 fmad(k.w[0] * rho, fmad(-keep, e.even0, f.even0), fmad(k.orest[0], drho, k.oeoff[0])));
+#pragma unroll
+    for (int p = 0; p < Lattice<LAT>::NP; ++p) {
+        C even, odd, feven, fodd;
+        eq_parts<LAT, ORDER, C>(k, e, p, even, odd);
+        eq_parts<LAT, ORDER, C>(k, f, p, feven, fodd);
+        const C de = fmad(-keep, even, feven), dd = fmad(-keep, odd, fodd);
+        const C wr = k.w[p + 1] * rho;
+        const C obase = fmad(k.orest[p + 1], drho, k.oeoff[p + 1]);
+        gp[p + 1] = fmad(keep, gp[p + 1], fmad(wr, de + dd, obase));
+        gm[p + 1] = fmad(keep, gm[p + 1], fmad(wr, de - dd, obase));
+    }
+}
+
 template <int LAT, typename C> __device__ inline void moments_of(const C *gp, const C *gm, C &drho, C &jx, C &jy, C &jz)
 {
     using L = Lattice<LAT>;
@@ -491,11 +519,14 @@ __device__ inline void close_moments(C *eqp, C *eqm, C drho, C jx, C jy, C jz)
 
 // One BGK collision of eq:LBE_BGK on the pre-collision deviations of a cell (rest in gp[0],
 // pair p in gp[p+1] / gm[p+1]); the arrays receive the post-collision deviations. With FORCE
-// and k.forced set, the body force is added by the exact-difference method,
-// g* = g + w (g^eq(rho, s) - g) + [g^eq(rho, s + F/rho) - g^eq(rho, s)], evaluated as the one
-// fused multiply-add g* = (1 - w) (g - g^eq(rho, s)) + g^eq(rho, s + F/rho) per direction (the
-// same value in exact arithmetic, two operations fewer). CLOSE applies close_moments to the
-// equilibria; it
+// the body force is added by the exact-difference method,
+// g* = g + w (g^eq(rho, s) - g) + [g^eq(rho, s + F/rho) - g^eq(rho, s)]
+//    = (1 - w) (g - g^eq(rho, s)) + g^eq(rho, s + F/rho).
+// With CLOSE (FP32 storage) both equilibria are assembled and closed, and the second form is
+// one fused multiply-add per direction; it runs only when k.forced is set. Without the closure
+// relax_forced_pairs evaluates it from the equilibria's even and odd parts, whether or not a
+// force is set (F = 0 then gives plain BGK): one code path keeps the register count of these
+// kernels down. CLOSE applies close_moments to the equilibria; it
 // matters where the stored deviations keep FP32 resolution (FP32 storage). With 16-bit storage
 // each step's rounding of the deviations is about four orders above the drift the closure
 // removes, so those kernels skip it (measured: FP16 e(s) 2.23e-3 with, 2.25e-3 without, after
@@ -509,10 +540,14 @@ __device__ inline void collide_cell(const StepConsts<C> &k, C *gp, C *gm)
     const C rho = k.rho0 + drho;
     const C inv = C(1) / rho;
     if constexpr (!CLOSE && !FORCE) {
-        // without the closure g^eq itself is not needed: relax against omega g^eq directly.
-        // (Kernels with the force keep one relaxation form: a second one, with its own set of
-        // constants, took the D3Q27 FP64 masked step from 208 to 255 VGPRs.)
+        // without the closure g^eq itself is not needed: relax against omega g^eq directly
         relax_pairs<LAT, ORDER, C>(k, drho, rho, jx * inv, jy * inv, jz * inv, gp, gm);
+        return;
+    }
+    if constexpr (!CLOSE && FORCE) {
+        // one form whether or not a force is set: a runtime branch between two forms took the
+        // D3Q27 FP64 masked step from 208 to 255 VGPRs
+        relax_forced_pairs<LAT, ORDER, C>(k, drho, rho, inv, jx, jy, jz, gp, gm);
         return;
     }
     C eqp[NP + 1], eqm[NP + 1];
