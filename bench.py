@@ -90,6 +90,8 @@ LEGS = {
     "step-f64": ("D3Q19 256^3 FP64 step", "step", "f64"),
     "porous-f32": ("D3Q27 porous medium 512^3, FP32 (links step with body force)", "porous", "f32"),
     "porous-f16": ("D3Q27 porous medium 512^3, FP16-shifted (links step with body force)", "porous", "f16"),
+    "porous-bf16": ("D3Q27 porous medium 512^3, BF16-shifted (links step with body force)", "porous", "bf16"),
+    "porous-f64": ("D3Q27 porous medium 512^3, FP64 (links step with body force)", "porous", "f64"),
     "adjoint-d3q19": ("gradient workload D3Q19 128^3, FP32: lbm_grad over --steps steps", "adjoint", "f32"),
     "batched": ("512 batched D3Q19 domains, FP32, step per launch (domain-major tiles)", "batched", "f32"),
     "batched-xcd": ("512 batched D3Q19 domains, FP32, step per launch (each domain's tiles on one XCD)", "batched",

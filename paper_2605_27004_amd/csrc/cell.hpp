@@ -430,23 +430,34 @@ __device__ inline void relax_pairs(const StepConsts<C> &k, C drho, C rho, C sx, 
     }
 }
 
-// BGK with the exact-difference force, g* = (1 - omega) (g - g^eq(s)) + g^eq(s + F/rho), for
-// kernels without the closure. The two equilibria share w rho and the constant part, so with
-// E, O the even and odd parts at s and E', O' at s + F/rho each pair member is
+// BGK with the exact-difference force, g* = (1 - omega) (g - g^eq(s)) + g^eq(s + F/rho). The
+// two equilibria share w rho and the constant part, so with E, O the even and odd parts at s
+// and E', O' at s + F/rho each pair member is
 // g*+- = (1 - omega) g+- + w rho [(E' - (1 - omega) E) +- (O' - (1 - omega) O)] + omega base:
-// the pair's two differences are formed once and neither equilibrium is assembled.
-template <int LAT, int ORDER, typename C>
+// the pair's two differences are formed once and neither equilibrium is assembled. With F = 0
+// this is plain BGK.
+// CLOSE (FP32 storage) then closes the conserved moments of g* itself: the axis pairs take the
+// difference between j + F and the momentum of g*, and the rest population takes drho minus
+// the other populations, so sum_i g*_i = drho and sum_i g*_i c_i = j + F hold up to
+// per-operation rounding. In exact arithmetic these are the corrections that closing each
+// equilibrium on its own momentum (close_moments) carries into g*: the FP32 constants' rounding
+// is removed the same way, without assembling and closing two equilibria.
+template <int LAT, int ORDER, bool CLOSE, typename C>
 __device__ inline void relax_forced_pairs(const StepConsts<C> &k, C drho, C rho, C inv, C jx, C jy, C jz, C *gp,
                                           C *gm)
 {
+    using L = Lattice<LAT>;
+    const C fjx = jx + k.force[0], fjy = jy + k.force[1], fjz = jz + k.force[2];
     const EqCell<C> e = eq_cell(k, drho, rho, jx * inv, jy * inv, jz * inv);
-    const EqCell<C> f = eq_cell(k, drho, rho, (jx + k.force[0]) * inv, (jy + k.force[1]) * inv,
-                                (jz + k.force[2]) * inv);
+    const EqCell<C> f = eq_cell(k, drho, rho, fjx * inv, fjy * inv, fjz * inv);
     const C keep = k.keep;
-    gp[0] = fmad(keep, gp[0],
-                 fmad(k.w[0] * rho, fmad(-keep, e.even0, f.even0), fmad(k.orest[0], drho, k.oeoff[0])));
+    if constexpr (!CLOSE)
+        gp[0] = fmad(keep, gp[0],
+                     fmad(k.w[0] * rho, fmad(-keep, e.even0, f.even0), fmad(k.orest[0], drho, k.oeoff[0])));
+    C mass = C(0), mx = C(0), my = C(0), mz = C(0);
+    bool bx = false, by = false, bz = false;
 #pragma unroll
-    for (int p = 0; p < Lattice<LAT>::NP; ++p) {
+    for (int p = 0; p < L::NP; ++p) {
         C even, odd, feven, fodd;
         eq_parts<LAT, ORDER, C>(k, e, p, even, odd);
         eq_parts<LAT, ORDER, C>(k, f, p, feven, fodd);
@@ -455,6 +466,31 @@ __device__ inline void relax_forced_pairs(const StepConsts<C> &k, C drho, C rho,
         const C obase = fmad(k.orest[p + 1], drho, k.oeoff[p + 1]);
         gp[p + 1] = fmad(keep, gp[p + 1], fmad(wr, de + dd, obase));
         gm[p + 1] = fmad(keep, gm[p + 1], fmad(wr, de - dd, obase));
+        if constexpr (CLOSE) {
+            // mass and momentum of g*, each from its first term
+            const PairRow v = L::pair(p);
+            const C sum = gp[p + 1] + gm[p + 1], dif = gp[p + 1] - gm[p + 1];
+            mass = p == 0 ? sum : mass + sum;
+            if (v.cx != 0) mx = bx ? (v.cx > 0 ? mx + dif : mx - dif) : (v.cx > 0 ? dif : -dif), bx = true;
+            if (v.cy != 0) my = by ? (v.cy > 0 ? my + dif : my - dif) : (v.cy > 0 ? dif : -dif), by = true;
+            if (v.cz != 0) mz = bz ? (v.cz > 0 ? mz + dif : mz - dif) : (v.cz > 0 ? dif : -dif), bz = true;
+        }
+    }
+    if constexpr (CLOSE) {
+        static_assert(L::pair(0).cx == 1 && L::pair(1).cy == 1, "axis pairs come first");
+        const C hx = C(0.5) * (fjx - mx);
+        const C hy = C(0.5) * (fjy - my);
+        gp[1] += hx;
+        gm[1] -= hx;
+        gp[2] += hy;
+        gm[2] -= hy;
+        if constexpr (L::D == 3) {
+            static_assert(L::D == 2 || L::pair(2).cz == 1, "axis pairs come first");
+            const C hz = C(0.5) * (fjz - mz);
+            gp[3] += hz;
+            gm[3] -= hz;
+        }
+        gp[0] = drho - mass;
     }
 }
 
@@ -521,12 +557,11 @@ __device__ inline void close_moments(C *eqp, C *eqm, C drho, C jx, C jy, C jz)
 // pair p in gp[p+1] / gm[p+1]); the arrays receive the post-collision deviations. With FORCE
 // the body force is added by the exact-difference method,
 // g* = g + w (g^eq(rho, s) - g) + [g^eq(rho, s + F/rho) - g^eq(rho, s)]
-//    = (1 - w) (g - g^eq(rho, s)) + g^eq(rho, s + F/rho).
-// With CLOSE (FP32 storage) both equilibria are assembled and closed, and the second form is
-// one fused multiply-add per direction; it runs only when k.forced is set. Without the closure
-// relax_forced_pairs evaluates it from the equilibria's even and odd parts, whether or not a
-// force is set (F = 0 then gives plain BGK): one code path keeps the register count of these
-// kernels down. CLOSE applies close_moments to the equilibria; it
+//    = (1 - w) (g - g^eq(rho, s)) + g^eq(rho, s + F/rho),
+// which relax_forced_pairs evaluates from the two equilibria's even and odd parts, whether or
+// not a force is set (F = 0 then gives plain BGK): one code path keeps the register count of
+// these kernels down. CLOSE closes the conserved moments (close_moments on the equilibrium, or
+// on g* in relax_forced_pairs); it
 // matters where the stored deviations keep FP32 resolution (FP32 storage). With 16-bit storage
 // each step's rounding of the deviations is about four orders above the drift the closure
 // removes, so those kernels skip it (measured: FP16 e(s) 2.23e-3 with, 2.25e-3 without, after
@@ -544,33 +579,15 @@ __device__ inline void collide_cell(const StepConsts<C> &k, C *gp, C *gm)
         relax_pairs<LAT, ORDER, C>(k, drho, rho, jx * inv, jy * inv, jz * inv, gp, gm);
         return;
     }
-    if constexpr (!CLOSE && FORCE) {
+    if constexpr (FORCE) {
         // one form whether or not a force is set: a runtime branch between two forms took the
         // D3Q27 FP64 masked step from 208 to 255 VGPRs
-        relax_forced_pairs<LAT, ORDER, C>(k, drho, rho, inv, jx, jy, jz, gp, gm);
+        relax_forced_pairs<LAT, ORDER, CLOSE, C>(k, drho, rho, inv, jx, jy, jz, gp, gm);
         return;
     }
     C eqp[NP + 1], eqm[NP + 1];
     equilibrium_pairs<LAT, ORDER, C>(k, drho, rho, jx * inv, jy * inv, jz * inv, eqp, eqm);
     if constexpr (CLOSE) close_moments<LAT>(eqp, eqm, drho, jx, jy, jz);
-    if constexpr (FORCE) {
-        if (k.forced) {
-            // both equilibria closed (in FP32) on their own momenta, j + F and j, so the
-            // increment carries exactly F and no mass
-            const C fjx = jx + k.force[0], fjy = jy + k.force[1], fjz = jz + k.force[2];
-            C fqp[NP + 1], fqm[NP + 1];
-            equilibrium_pairs<LAT, ORDER, C>(k, drho, rho, fjx * inv, fjy * inv, fjz * inv, fqp, fqm);
-            if constexpr (CLOSE) close_moments<LAT>(fqp, fqm, drho, fjx, fjy, fjz);
-            const C keep = C(1) - k.omega;
-            gp[0] = fmad(keep, gp[0] - eqp[0], fqp[0]);
-#pragma unroll
-            for (int p = 0; p < NP; ++p) {
-                gp[p + 1] = fmad(keep, gp[p + 1] - eqp[p + 1], fqp[p + 1]);
-                gm[p + 1] = fmad(keep, gm[p + 1] - eqm[p + 1], fqm[p + 1]);
-            }
-            return;
-        }
-    }
     gp[0] = fmad(k.omega, eqp[0] - gp[0], gp[0]);
 #pragma unroll
     for (int p = 0; p < NP; ++p) {

@@ -927,40 +927,36 @@ __device__ inline void adjoint_cell(const S *__restrict__ state, const typename 
     }
 }
 
-// One reverse step over the grid. Work-group (bx, by) takes tile column bx of the rows
-// [by per, (by + 1) per) of the flattened (y-tile, z) order; each lane accumulates its cells'
-// G / d tau in FP64 and the work-group adds its sums to gpart (in the same order every step,
-// so the totals are reproducible).
+// One reverse step over the grid, one row tile (a y-tile of one z-plane, 256 cells) per
+// work-group: each lane's G / d tau go to FP64 and the work-group adds its sums to its own
+// entries of gpart (in the same order every step, so the totals are reproducible). With no sums
+// carried from row to row the D3Q19 FP32 kernel needs 113 VGPRs (4 waves per SIMD). Work-groups
+// of several row tiles, carrying per-lane FP64 sums across the rows, measured slower at 128^3:
+// 95 us per step for one row against 107.5 (2 rows), 109 (4) and 112 (11) with the sums in
+// registers (138 VGPRs), and 103 (2 rows) with the sums in LDS.
 template <int LAT, typename S, int ORDER, bool FORCED, bool LINKS>
 __global__ __launch_bounds__(256) void k_adjoint(const S *__restrict__ state, const typename Conv<S>::C *__restrict__ lam_in,
                                                  typename Conv<S>::C *__restrict__ lam_out,
                                                  const float *__restrict__ gray, const uint32_t *__restrict__ links,
                                                  double *__restrict__ dmask, double *__restrict__ gpart, const Grid g,
-                                                 const StepConsts<typename Conv<S>::C> k, const uint32_t per)
+                                                 const StepConsts<typename Conv<S>::C> k, const uint32_t tiles_x)
 {
     using C = typename Conv<S>::C;
     constexpr int kWaves = 256 / 64;
     __shared__ double red[kGradPartials][kWaves];
     const int tid = threadIdx.y * blockDim.x + threadIdx.x;
     const uint32_t tiles_y = ((uint32_t)g.ny + blockDim.y - 1u) / blockDim.y;
-    const uint32_t rows = tiles_y * (uint32_t)g.nz;
-    const uint32_t f0 = blockIdx.y * per;
-    const uint32_t f1 = f0 + per < rows ? f0 + per : rows;
+    const uint32_t f = blockIdx.x / tiles_x;  // the row tile: y-tile f % tiles_y of z-plane f / tiles_y
+    const int32_t x = (int32_t)((blockIdx.x % tiles_x) * blockDim.x + threadIdx.x);
+    const int32_t y = (int32_t)((f % tiles_y) * blockDim.y + threadIdx.y);
+    const int32_t z = (int32_t)(f / tiles_y);
+    C G[6] = {C(0), C(0), C(0), C(0), C(0), C(0)};
+    C dtau = C(0);
+    adjoint_cell<LAT, S, ORDER, FORCED, LINKS>(state, lam_in, lam_out, gray, links, dmask, g, k, x, y, z, G, dtau);
     double v[kGradPartials];
 #pragma unroll
-    for (int e = 0; e < kGradPartials; ++e) v[e] = 0.0;
-    for (uint32_t f = f0; f < f1; ++f) {
-        const int32_t z = (int32_t)(f / tiles_y);
-        const int32_t x = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
-        const int32_t y = (int32_t)((f % tiles_y) * blockDim.y + threadIdx.y);
-        C G[6] = {C(0), C(0), C(0), C(0), C(0), C(0)};
-        C dtau = C(0);
-        adjoint_cell<LAT, S, ORDER, FORCED, LINKS>(state, lam_in, lam_out, gray, links, dmask, g, k, x, y, z, G,
-                                                   dtau);
-#pragma unroll
-        for (int e = 0; e < 6; ++e) v[e] += (double)G[e];
-        v[6] += (double)dtau;
-    }
+    for (int e = 0; e < 6; ++e) v[e] = (double)G[e];
+    v[6] = (double)dtau;
     // work-group sums of G and d tau: within each wave by lane exchange, then across the waves
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1)
@@ -974,8 +970,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const S *__restrict__ state, co
         double t = red[tid][0];
 #pragma unroll
         for (int wv = 1; wv < kWaves; ++wv) t += red[tid][wv];
-        const uint32_t b = blockIdx.y * gridDim.x + blockIdx.x;
-        gpart[kGradPartials * (size_t)b + tid] += t;
+        gpart[kGradPartials * (size_t)blockIdx.x + tid] += t;
     }
 }
 
@@ -1076,6 +1071,16 @@ hipError_t launch_init(int lattice, int storage, int order, const Grid &g, const
     });
 }
 
+// LDS that a launch of the FP32 links step reserves without using it: at most 4 work-groups
+// then fit in a compute unit's 160 KiB of LDS. The kernel needs 80 VGPRs, so 6 would otherwise be
+// resident, and the extra work-groups in flight cost more in re-fetched cache lines than they
+// hide (D3Q27 512^3 porous medium: 4,962 us per step with 6 resident, 4,851 with 4, 4,890 with 3
+// and 4,882 with 5).
+template <typename S, int M> constexpr unsigned links_lds()
+{
+    return (M == kLinks && std::is_same<S, float>::value) ? 160u * 1024u / 5u + 1024u : 0u;
+}
+
 hipError_t launch_step(int lattice, int storage, int order, const Grid &g, const StepConsts<double> &k64,
                        const StepConsts<float> &k32, const uint32_t *links, const float *gray, const void *src,
                        void *dst, int block_x, int block_y, int flags, hipStream_t stream)
@@ -1110,8 +1115,8 @@ hipError_t launch_step(int lattice, int storage, int order, const Grid &g, const
                 break;                                                                                           \
             }                                                                                                    \
         }                                                                                                        \
-        hipLaunchKernelGGL((k_step<LAT, S, O, M, kPullShifted>), grid, block, 0, stream, in, out, g, *kc, m, links, \
-                           gray);                                                                                \
+        hipLaunchKernelGGL((k_step<LAT, S, O, M, kPullShifted>), grid, block, (links_lds<S, M>()), stream, in, out, g, \
+                           *kc, m, links, gray);                                                                 \
     } while (0)
             if (mode == kStream) {
                 LBM_STEP(3, kStream);
@@ -1130,27 +1135,11 @@ hipError_t launch_step(int lattice, int storage, int order, const Grid &g, const
     });
 }
 
-// Rows (a y-tile of one z-plane) per work-group of the adjoint launch: up to 4, enough to
-// amortise the FP64 work-group reduction of the sensitivities over several cells per lane,
-// while keeping at least 2048 work-groups (8 per compute unit) where the grid has them.
-uint32_t adjoint_rows_per_group(const Grid &g)
-{
-    const dim3 t = row_grid(g);
-    const uint32_t per = t.x * t.y * t.z / 2048u;
-    return per < 1u ? 1u : (per > 4u ? 4u : per);
-}
-
-dim3 adjoint_grid(const Grid &g)
-{
-    const dim3 t = row_grid(g);
-    const uint32_t rows = t.y * t.z, per = adjoint_rows_per_group(g);
-    return dim3(t.x, (rows + per - 1u) / per, 1u);
-}
-
+// The adjoint launch: one work-group per row tile, in a one-dimensional grid.
 uint32_t adjoint_blocks(const Grid &g)
 {
-    const dim3 grid = adjoint_grid(g);
-    return grid.x * grid.y;
+    const dim3 t = row_grid(g);
+    return t.x * t.y * t.z;
 }
 
 uint32_t row_blocks(const Grid &g)
@@ -1234,11 +1223,11 @@ hipError_t launch_adjoint(int lattice, int storage, int order, const Grid &g, co
             constexpr int LAT = decltype(lat)::value;
             const StepConsts<C> *kc;
             if constexpr (sizeof(C) == 8) kc = &k64; else kc = &k32;
-            const dim3 grid = adjoint_grid(g), block = row_block(g);
-            const uint32_t per = adjoint_rows_per_group(g);
+            const dim3 grid(adjoint_blocks(g)), block = row_block(g);
+            const uint32_t tiles_x = row_grid(g).x;
 #define LBM_ADJ(O, F, L)                                                                                         \
     hipLaunchKernelGGL((k_adjoint<LAT, S, O, F, L>), grid, block, 0, stream, (const S *)state, (const C *)lam_in,  \
-                       (C *)lam_out, gray, links, dmask, gpart, g, *kc, per)
+                       (C *)lam_out, gray, links, dmask, gpart, g, *kc, tiles_x)
 #define LBM_ADJ_L(O, F)                                                                                          \
     do {                                                                                                         \
         if (links) LBM_ADJ(O, F, true); else LBM_ADJ(O, F, false);                                               \
