@@ -529,6 +529,14 @@ __device__ inline NuMoments<C> nu_moments(const StepConsts<C> &k, const C *mup, 
     using L = Lattice<LAT>;
     NuMoments<C> m;
     m.ref = keep * mup[0];
+    // every sum starts from its first term (IEEE arithmetic keeps a leading 0 + x as an
+    // instruction); the flags are constants after unrolling
+    bool b0 = false, b1[3] = {false, false, false}, b2[6] = {false, false, false, false, false, false};
+    bool b3[7] = {false, false, false, false, false, false, false};
+    const auto add = [](C &acc, bool &started, C v, bool neg) {
+        acc = started ? (neg ? acc - v : acc + v) : (neg ? -v : v);
+        started = true;
+    };
     m.m0 = C(0);
 #pragma unroll
     for (int a = 0; a < 3; ++a) m.m1[a] = C(0);
@@ -545,33 +553,29 @@ __device__ inline NuMoments<C> nu_moments(const StepConsts<C> &k, const C *mup, 
         const C sum = fmad(keep, mup[p + 1] + mum[p + 1], C(-2) * m.ref) * k.w[p + 1];
         const C dif = (keep * (mup[p + 1] - mum[p + 1])) * k.w[p + 1];
         const int c[3] = {v.cx, v.cy, v.cz};
-        m.m0 += sum;
+        add(m.m0, b0, sum, false);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            if (c[a] > 0) m.m1[a] += dif;
-            if (c[a] < 0) m.m1[a] -= dif;
-            if (c[a] != 0) m.m2[a] += sum;
+            if (c[a] != 0) add(m.m1[a], b1[a], dif, c[a] < 0);
+            if (c[a] != 0) add(m.m2[a], b2[a], sum, false);
         }
         const int ab[3][2] = {{0, 1}, {0, 2}, {1, 2}};
 #pragma unroll
         for (int e = 0; e < 3; ++e) {
             const int cc = c[ab[e][0]] * c[ab[e][1]];
-            if (cc > 0) m.m2[3 + e] += sum;
-            if (cc < 0) m.m2[3 + e] -= sum;
+            if (cc != 0) add(m.m2[3 + e], b2[3 + e], sum, cc < 0);
         }
         // M3_aab: index 2a + (b > a ? b - 1 : b) over b != a, i.e. xxy xxz yyx yyz zzx zzy
 #pragma unroll
         for (int a = 0; a < 3; ++a)
 #pragma unroll
             for (int b = 0; b < 3; ++b) {
-                if (a == b || c[a] == 0) continue;
+                if (a == b || c[a] == 0 || c[b] == 0) continue;
                 const int e = 2 * a + (b > a ? b - 1 : b);
-                if (c[b] > 0) m.m3[e] += dif;
-                if (c[b] < 0) m.m3[e] -= dif;
+                add(m.m3[e], b3[e], dif, c[b] < 0);
             }
         const int cxyz = c[0] * c[1] * c[2];
-        if (cxyz > 0) m.m3[6] += dif;
-        if (cxyz < 0) m.m3[6] -= dif;
+        if (cxyz != 0) add(m.m3[6], b3[6], dif, cxyz < 0);
     }
     return m;
 }
@@ -905,15 +909,20 @@ __device__ inline void adjoint_cell(const S *__restrict__ state, const typename 
         for (int p = 0; p < NP; ++p) {
             C ep, em;
             eq_pair<LAT, ORDER, C>(k, e, p, ep, em);
-            C bp = fmad(w, ep - gp[p + 1], gp[p + 1]);
-            C bm = fmad(w, em - gm[p + 1], gm[p + 1]);
-            dtau = fmad(fmad(keep, mup[p + 1], -nm.ref), ep - gp[p + 1], dtau);
-            dtau = fmad(fmad(keep, mum[p + 1], -nm.ref), em - gm[p + 1], dtau);
+            const C dp = ep - gp[p + 1], dq = em - gm[p + 1];
+            dtau = fmad(fmad(keep, mup[p + 1], -nm.ref), dp, dtau);
+            dtau = fmad(fmad(keep, mum[p + 1], -nm.ref), dq, dtau);
+            // b = g + w (g^eq - g), plus g^eq(s + F/rho) - g^eq(s) with the force:
+            // b = (1 - w) (g - g^eq(s)) + g^eq(s + F/rho)
+            C bp, bm;
             if constexpr (FORCED) {
                 C fp, fm;
                 eq_pair<LAT, ORDER, C>(k, ef, p, fp, fm);
-                bp += fp - ep;
-                bm += fm - em;
+                bp = fmad(-om, dp, fp);
+                bm = fmad(-om, dq, fm);
+            } else {
+                bp = fmad(w, dp, gp[p + 1]);
+                bm = fmad(w, dq, gm[p + 1]);
             }
             const PairRow v = L::pair(p);
             const C vc = (C)v.cx * ax + (C)v.cy * ay + (C)v.cz * az;
@@ -942,8 +951,6 @@ __global__ __launch_bounds__(256) void k_adjoint(const S *__restrict__ state, co
                                                  const StepConsts<typename Conv<S>::C> k, const uint32_t tiles_x)
 {
     using C = typename Conv<S>::C;
-    constexpr int kWaves = 256 / 64;
-    __shared__ double red[kGradPartials][kWaves];
     const int tid = threadIdx.y * blockDim.x + threadIdx.x;
     const uint32_t tiles_y = ((uint32_t)g.ny + blockDim.y - 1u) / blockDim.y;
     const uint32_t f = blockIdx.x / tiles_x;  // the row tile: y-tile f % tiles_y of z-plane f / tiles_y
@@ -953,23 +960,26 @@ __global__ __launch_bounds__(256) void k_adjoint(const S *__restrict__ state, co
     C G[6] = {C(0), C(0), C(0), C(0), C(0), C(0)};
     C dtau = C(0);
     adjoint_cell<LAT, S, ORDER, FORCED, LINKS>(state, lam_in, lam_out, gray, links, dmask, g, k, x, y, z, G, dtau);
-    double v[kGradPartials];
+    // work-group sums of G and d tau through LDS in a fixed order: 224 lanes add 8 lane values
+    // each, then one lane per quantity adds those 32 sums
+    __shared__ double part[kGradPartials][256];
+    __shared__ double part2[kGradPartials][32];
 #pragma unroll
-    for (int e = 0; e < 6; ++e) v[e] = (double)G[e];
-    v[6] = (double)dtau;
-    // work-group sums of G and d tau: within each wave by lane exchange, then across the waves
+    for (int e = 0; e < 6; ++e) part[e][tid] = (double)G[e];
+    part[6][tid] = (double)dtau;
+    __syncthreads();
+    if (tid < kGradPartials * 32) {
+        const int e = tid >> 5, j = tid & 31;
+        double t = part[e][j];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-        for (int e = 0; e < kGradPartials; ++e) v[e] += __shfl_xor(v[e], off, 64);
-    if ((tid & 63) == 0)
-#pragma unroll
-        for (int e = 0; e < kGradPartials; ++e) red[e][tid >> 6] = v[e];
+        for (int r = 1; r < 8; ++r) t += part[e][j + 32 * r];
+        part2[e][j] = t;
+    }
     __syncthreads();
     if (tid < kGradPartials) {
-        double t = red[tid][0];
+        double t = part2[tid][0];
 #pragma unroll
-        for (int wv = 1; wv < kWaves; ++wv) t += red[tid][wv];
+        for (int j = 1; j < 32; ++j) t += part2[tid][j];
         gpart[kGradPartials * (size_t)blockIdx.x + tid] += t;
     }
 }
