@@ -243,8 +243,14 @@ struct PlaneStores {
 template <typename S> __device__ inline PlaneStores plane_stores(S *base, const Grid &g, const Ref &r)
 {
     PlaneStores ps;
-    // raw buffer: stride 0, the largest record count, the data format word of gfx9 raw buffers
-    ps.rsrc = __builtin_amdgcn_make_buffer_rsrc(base + r.zo, (short)0, -1, 0x00020000);
+    // raw buffer: stride 0, the largest record count, the data format word of gfx9 raw buffers.
+    // The base is the z-plane's, the same for the whole work-group; readfirstlane keeps it in
+    // scalar registers even where the compiler cannot prove that (otherwise every buffer access
+    // becomes a loop over the distinct descriptors of the wave)
+    const uint64_t a = reinterpret_cast<uint64_t>(base + r.zo);
+    const uint64_t u = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(a >> 32)) << 32) |
+                       (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)a);
+    ps.rsrc = __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<S *>(u), (short)0, -1, 0x00020000);
     ps.lane_off = r.idx * (uint32_t)sizeof(S);
     ps.plane_step = g.bc * (uint32_t)sizeof(S);
     return ps;
@@ -254,7 +260,10 @@ template <typename S> __device__ inline PlaneStores plane_stores(S *base, const 
 // default, for data read again soon).
 template <int AUX, typename S> __device__ inline void st_plane_aux(const PlaneStores &ps, int i, S v)
 {
-    const int soff = (int)((uint32_t)i * ps.plane_step);
+    // the scalar offset is uniform; readfirstlane says so where control flow has hidden it from
+    // the compiler (a value merged after a divergent branch), which would otherwise wrap the
+    // store in a loop over the distinct values
+    const int soff = __builtin_amdgcn_readfirstlane((int)((uint32_t)i * ps.plane_step));
     if constexpr (sizeof(S) == 2)
         __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), ps.rsrc, (int)ps.lane_off, soff, AUX);
     else if constexpr (sizeof(S) == 4)
