@@ -232,7 +232,8 @@ int lbm_set_launch(lbm_ctx *ctx, int32_t block_x, int32_t block_y, int32_t flags
  *   0  mass flux through the plane x = outlet_plane:  J = sum over its cells of (j_x + F_x/2)
  *   1  kinetic energy:                                J = sum over cells of |j + F/2|^2 / (2 rho)
  * with j = sum_i f_i c_i. The forward states are kept every checkpoint_every steps and each
- * segment is recomputed (bit-identically) before its reverse steps. The adjoint populations
+ * segment but the last is recomputed (bit-identically) before its reverse steps; the forward
+ * pass writes the last segment's states where the recompute would. The adjoint populations
  * use the arithmetic precision of the storage; the parameter sums are FP64.
  * Supported: every tensor kind (for LBM_TENSOR_ATILDE the derivative includes the det
  * normalisation) and every wall model: none, LBM_FLAG_GRAY, or LBM_FLAG_MASK (halfway

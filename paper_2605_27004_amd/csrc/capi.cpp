@@ -602,13 +602,28 @@ int lbm_grad(lbm_ctx *c, const lbm_grad_spec *spec, void *workspace, double *obj
     auto ckpt = [&](int64_t s) { return (void *)(ws + l.ckpt + s * pstride); };
     auto segst = [&](int64_t t) { return (void *)(ws + l.seg + (t - 1) * pstride); };  // t >= 1
 
-    // forward pass, keeping the state at the start of every segment
-    for (int64_t sgi = 0; sgi < l.nseg; ++sgi) {
-        e = hipMemcpyAsync(ckpt(sgi), c->pop[c->cur], popb, hipMemcpyDeviceToDevice, st);
+    // forward pass. Each step runs from one buffer into another, as in lbm_step, but the step
+    // that ends a segment writes straight into the next segment's checkpoint, and the steps of
+    // the last segment write straight into the segment buffer, from which the reverse sweep then
+    // takes that segment without recomputing it (the step is deterministic, so these are bitwise
+    // the states a recompute gives). Only the initial state is copied.
+    if (l.nseg > 0) {
+        e = hipMemcpyAsync(ckpt(0), c->pop[c->cur], popb, hipMemcpyDeviceToDevice, st);
         if (e != hipSuccess) return fail_hip(e, "checkpoint copy");
-        const int64_t len = std::min(spec->checkpoint_every, spec->nsteps - sgi * spec->checkpoint_every);
-        rc = lbm_step(c, len);
-        if (rc) return rc;
+        const void *src = ckpt(0);
+        for (int64_t sgi = 0; sgi < l.nseg; ++sgi) {
+            const int64_t len = std::min(spec->checkpoint_every, spec->nsteps - sgi * spec->checkpoint_every);
+            const bool last = sgi == l.nseg - 1;
+            for (int64_t t = 1; t <= len; ++t) {
+                void *dst = t == len ? (last ? c->pop[0] : ckpt(sgi + 1)) : (last ? segst(t) : c->pop[t & 1]);
+                e = launch_step(c->p.lattice, c->p.storage, c->p.order, c->grid, c->k64, c->k32, c->links, c->gray,
+                                src, dst, c->block_x, c->block_y, c->launch_flags, st);
+                if (e != hipSuccess) return fail_hip(e, "forward step");
+                src = dst;
+            }
+        }
+        c->cur = 0;
+        c->t += spec->nsteps;
     }
     // seed the reverse sweep with dJ/df at the final state
     void *lam_in = ws + l.lam_a, *lam_out = ws + l.lam_b;
@@ -623,7 +638,8 @@ int lbm_grad(lbm_ctx *c, const lbm_grad_spec *spec, void *workspace, double *obj
     for (int64_t sgi = l.nseg - 1; sgi >= 0; --sgi) {
         const int64_t len = std::min(spec->checkpoint_every, spec->nsteps - sgi * spec->checkpoint_every);
         auto state = [&](int64_t t) { return t == 0 ? ckpt(sgi) : segst(t); };
-        for (int64_t t = 1; t < len; ++t) {
+        // the last segment's states are already there from the forward pass
+        for (int64_t t = 1; t < len && sgi < l.nseg - 1; ++t) {
             e = launch_step(c->p.lattice, c->p.storage, c->p.order, c->grid, c->k64, c->k32, c->links, c->gray,
                             state(t - 1), state(t), c->block_x, c->block_y, c->launch_flags, st);
             if (e != hipSuccess) return fail_hip(e, "segment recompute");
