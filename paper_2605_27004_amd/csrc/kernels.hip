@@ -1081,14 +1081,24 @@ hipError_t launch_init(int lattice, int storage, int order, const Grid &g, const
     });
 }
 
-// LDS that a launch of the FP32 links step reserves without using it: at most 4 work-groups
-// then fit in a compute unit's 160 KiB of LDS. The kernel needs 80 VGPRs, so 6 would otherwise be
-// resident, and the extra work-groups in flight cost more in re-fetched cache lines than they
-// hide (D3Q27 512^3 porous medium: 4,962 us per step with 6 resident, 4,851 with 4, 4,890 with 3
-// and 4,882 with 5).
-template <typename S, int M> constexpr unsigned links_lds()
+// LDS that a step launch reserves without using it, to cap the work-groups resident on a
+// compute unit (160 KiB of LDS each): reserving a little over 160 KiB / (n + 1) leaves room
+// for n. Fewer work-groups in flight keep fewer rows' cache lines and HBM pages open at once;
+// measured (D3Q19 256^3 lane-exchange step, us per step, uncapped -> capped):
+//   FP32 at 4 per CU: 399.7 -> 390.7 (3: 390.8, 5: 394.0, 2: 429.7)
+//   FP64 at 2 per CU: 832.7 -> 803.7 (3: 817.3, 4: 827.3)
+//   FP16 and BF16 lose with any cap (4: 198 -> 215 and 222 us): their steps need the waves,
+//   and so does the gray step of the gradient workload (D3Q19 FP32 128^3, 3 per CU: 2.6% slower).
+// The FP32 links step (80 VGPRs, 6 resident) at 4 per CU: 4,962 -> 4,851 us on the 512^3
+// porous medium (3: 4,890, 5: 4,882), where the extra work-groups re-fetched lines.
+constexpr unsigned cap_lds(unsigned groups) { return 160u * 1024u / (groups + 1u) + 1024u; }
+
+template <typename S, int M, int PULL> constexpr unsigned step_lds()
 {
-    return (M == kLinks && std::is_same<S, float>::value) ? 160u * 1024u / 5u + 1024u : 0u;
+    constexpr bool f32 = std::is_same<S, float>::value, f64 = std::is_same<S, double>::value;
+    if (M == kLinks) return f32 ? cap_lds(4) : 0u;
+    if ((M == kPlain || M == kStream) && PULL == kPullRows) return f32 ? cap_lds(4) : (f64 ? cap_lds(2) : 0u);
+    return 0u;
 }
 
 hipError_t launch_step(int lattice, int storage, int order, const Grid &g, const StepConsts<double> &k64,
@@ -1120,12 +1130,12 @@ hipError_t launch_step(int lattice, int storage, int order, const Grid &g, const
     do {                                                                                                         \
         if constexpr (M != kLinks) {                                                                             \
             if (aligned) {                                                                                       \
-                hipLaunchKernelGGL((k_step<LAT, S, O, M, kPullRows>), grid, block, 0, stream, in, out, g, *kc, m, \
-                                   links, gray);                                                                 \
+                hipLaunchKernelGGL((k_step<LAT, S, O, M, kPullRows>), grid, block, (step_lds<S, M, kPullRows>()),  \
+                                   stream, in, out, g, *kc, m, links, gray);                                     \
                 break;                                                                                           \
             }                                                                                                    \
         }                                                                                                        \
-        hipLaunchKernelGGL((k_step<LAT, S, O, M, kPullShifted>), grid, block, (links_lds<S, M>()), stream, in, out, g, \
+        hipLaunchKernelGGL((k_step<LAT, S, O, M, kPullShifted>), grid, block, (step_lds<S, M, kPullShifted>()), stream, in, out, g, \
                            *kc, m, links, gray);                                                                 \
     } while (0)
             if (mode == kStream) {
