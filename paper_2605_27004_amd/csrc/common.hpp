@@ -97,6 +97,10 @@ hipError_t launch_zero(double *p, uint64_t n, hipStream_t stream);
 
 // rho / s may be null. partials: scratch of kPartials * moments_groups(g) doubles; totals:
 // kPartials doubles of scratch (sum drho, sum rho s_x, _y, _z, fluid cells).
+// LDS for a launch to reserve without using it so that at most `groups` work-groups share a
+// compute unit (160 KiB of LDS each on gfx950): a little over 160 KiB / (groups + 1).
+constexpr unsigned cap_lds(unsigned groups) { return 160u * 1024u / (groups + 1u) + 1024u; }
+
 constexpr int kPartials = 5;
 constexpr uint32_t kMomentGroups = 2048;  // most work-groups of a moments launch
 hipError_t launch_moments(int lattice, int storage, const Grid &g, const StepConsts<double> &k,
