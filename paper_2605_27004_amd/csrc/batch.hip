@@ -367,9 +367,10 @@ hipError_t launch_batch_step(int lattice, int storage, int order, uint32_t ntile
                 using C = typename Conv<S>::C;
                 const StepConsts<C> *kc;
                 if constexpr (sizeof(C) == 8) kc = k64; else kc = k32;
-                // FP32: at most 4 work-groups per compute unit (reserved LDS, as for the single-grid
-                // step): 512 D3Q19 domains 817 -> 785 us per step (3: 842, 5: 802)
-                const unsigned lds = std::is_same<S, float>::value ? cap_lds(4) : 0u;
+                // FP32 / FP64: the resident work-groups of a single-grid step (stream_groups, reserved
+                // LDS); 512 D3Q19 FP32 domains 817 -> 785 us per step at 4 (3: 842, 5: 802)
+                constexpr bool wide = std::is_same<S, float>::value || std::is_same<S, double>::value;
+                const unsigned lds = wide ? stream_lds(Lattice<decltype(lat)::value>::Q, sizeof(S)) : 0u;
                 hipLaunchKernelGGL((k_batch_step<decltype(lat)::value, S, decltype(ord)::value>), dim3(ntiles),
                                    dim3(kTileCells), lds, stream, (const S *)src, (S *)dst, tiles, doms, kc);
                 return hipGetLastError();

@@ -101,6 +101,25 @@ hipError_t launch_zero(double *p, uint64_t n, hipStream_t stream);
 // compute unit (160 KiB of LDS each on gfx950): a little over 160 KiB / (groups + 1).
 constexpr unsigned cap_lds(unsigned groups) { return 160u * 1024u / (groups + 1u) + 1024u; }
 
+// Work-groups per compute unit for an FP32 or FP64 streaming step (256-cell tiles, q pulls of
+// `bytes` each per cell): the count that keeps about 78 KiB of pulls in flight per compute
+// unit, at least 2. Measured best caps (D3Q19 and D3Q27 256^3, D2Q9 256 x 65536): D3Q19 FP32 4,
+// D3Q19 FP64 2, D3Q27 FP32 3, D3Q27 FP64 2 (1 is far slower), D2Q9 FP64 4; D2Q9 FP32 gains
+// nothing from a cap (the rule gives 9, more than ever fit).
+constexpr unsigned stream_groups(unsigned q, unsigned bytes)
+{
+    const unsigned per = 256u * q * bytes;
+    const unsigned n = (79872u + per / 2u) / per;
+    return n < 2u ? 2u : n;
+}
+constexpr unsigned stream_lds(unsigned q, unsigned bytes)
+{
+    return stream_groups(q, bytes) >= 8u ? 0u : cap_lds(stream_groups(q, bytes));
+}
+static_assert(stream_groups(19, 4) == 4 && stream_groups(19, 8) == 2 && stream_groups(27, 4) == 3 &&
+                  stream_groups(27, 8) == 2 && stream_groups(9, 8) == 4 && stream_lds(9, 4) == 0,
+              "the measured caps");
+
 constexpr int kPartials = 5;
 constexpr uint32_t kMomentGroups = 2048;  // most work-groups of a moments launch
 hipError_t launch_moments(int lattice, int storage, const Grid &g, const StepConsts<double> &k,

@@ -1082,21 +1082,23 @@ hipError_t launch_init(int lattice, int storage, int order, const Grid &g, const
 }
 
 // LDS that a step launch reserves without using it (cap_lds), to cap the work-groups resident
-// on a compute unit. Fewer work-groups in flight keep fewer rows' cache lines and HBM pages open at once;
-// measured (D3Q19 256^3 lane-exchange step, us per step, uncapped -> capped):
+// on a compute unit. Fewer work-groups in flight keep fewer rows' cache lines and HBM pages open
+// at once. FP32 and FP64 streaming steps take stream_groups(q, sizeof(S)); measured on the
+// D3Q19 256^3 lane-exchange step (us per step, uncapped -> capped):
 //   FP32 at 4 per CU: 399.7 -> 390.7 (3: 390.8, 5: 394.0, 2: 429.7)
 //   FP64 at 2 per CU: 832.7 -> 803.7 (3: 817.3, 4: 827.3)
-//   FP16 and BF16 lose with any cap (4: 198 -> 215 and 222 us): their steps need the waves,
-//   and so does the gray step of the gradient workload (D3Q19 FP32 128^3, 3 per CU: 2.6% slower).
+// and D3Q27 256^3 FP32 at 3: 571.5 -> 556 (FP64 at 2: 1,205 -> 1,171.5), D2Q9 256 x 65536 FP64
+// at 4: 378.9 -> 368.5. FP16 and BF16 lose with any cap (4 per CU: 198 -> 215 and 222 us; D3Q27
+// FP16 at 5: no change): their steps issue more instructions per byte and need the waves, and so
+// does the gray step of the gradient workload (D3Q19 FP32 128^3, 3 per CU: 2.6% slower).
 // The FP32 links step (80 VGPRs, 6 resident) at 4 per CU: 4,962 -> 4,851 us on the 512^3
 // porous medium (3: 4,890, 5: 4,882), where the extra work-groups re-fetched lines. Rows longer
 // than a work-group (shifted pulls), FP32 at 4 per CU: 512^3 3,388 -> 3,339 us, 384^3 unchanged.
-template <typename S, int M, int PULL> constexpr unsigned step_lds()
+template <int LAT, typename S, int M> constexpr unsigned step_lds()
 {
     constexpr bool f32 = std::is_same<S, float>::value, f64 = std::is_same<S, double>::value;
     if (M == kLinks) return f32 ? cap_lds(4) : 0u;
-    if ((M == kPlain || M == kStream) && PULL == kPullRows) return f32 ? cap_lds(4) : (f64 ? cap_lds(2) : 0u);
-    if ((M == kPlain || M == kStream) && PULL == kPullShifted) return f32 ? cap_lds(4) : 0u;
+    if (M == kPlain || M == kStream) return (f32 || f64) ? stream_lds(Lattice<LAT>::Q, sizeof(S)) : 0u;
     return 0u;
 }
 
@@ -1129,12 +1131,12 @@ hipError_t launch_step(int lattice, int storage, int order, const Grid &g, const
     do {                                                                                                         \
         if constexpr (M != kLinks) {                                                                             \
             if (aligned) {                                                                                       \
-                hipLaunchKernelGGL((k_step<LAT, S, O, M, kPullRows>), grid, block, (step_lds<S, M, kPullRows>()),  \
+                hipLaunchKernelGGL((k_step<LAT, S, O, M, kPullRows>), grid, block, (step_lds<LAT, S, M>()),  \
                                    stream, in, out, g, *kc, m, links, gray);                                     \
                 break;                                                                                           \
             }                                                                                                    \
         }                                                                                                        \
-        hipLaunchKernelGGL((k_step<LAT, S, O, M, kPullShifted>), grid, block, (step_lds<S, M, kPullShifted>()), stream, in, out, g, \
+        hipLaunchKernelGGL((k_step<LAT, S, O, M, kPullShifted>), grid, block, (step_lds<LAT, S, M>()), stream, in, out, g, \
                            *kc, m, links, gray);                                                                 \
     } while (0)
             if (mode == kStream) {
