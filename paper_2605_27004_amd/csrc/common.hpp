@@ -98,27 +98,34 @@ hipError_t launch_zero(double *p, uint64_t n, hipStream_t stream);
 // rho / s may be null. partials: scratch of kPartials * moments_groups(g) doubles; totals:
 // kPartials doubles of scratch (sum drho, sum rho s_x, _y, _z, fluid cells).
 // LDS for a launch to reserve without using it so that at most `groups` work-groups share a
-// compute unit (160 KiB of LDS each on gfx950): a little over 160 KiB / (groups + 1).
-constexpr unsigned cap_lds(unsigned groups) { return 160u * 1024u / (groups + 1u) + 1024u; }
+// compute unit (160 KiB of LDS each on gfx950): a little over 160 KiB / (groups + 1). LDS is
+// allocated in 512-byte blocks, so `groups` of them still fit for up to 17 groups.
+constexpr unsigned cap_lds(unsigned groups) { return 160u * 1024u / (groups + 1u) + 512u; }
 
-// Work-groups per compute unit for an FP32 or FP64 streaming step (256-cell tiles, q pulls of
-// `bytes` each per cell): the count that keeps about 78 KiB of pulls in flight per compute
-// unit, at least 2. Measured best caps (D3Q19 and D3Q27 256^3, D2Q9 256 x 65536): D3Q19 FP32 4,
-// D3Q19 FP64 2, D3Q27 FP32 3, D3Q27 FP64 2 (1 is far slower), D2Q9 FP64 4; D2Q9 FP32 gains
-// nothing from a cap (the rule gives 9, more than ever fit).
-constexpr unsigned stream_groups(unsigned q, unsigned bytes)
+// Work-groups per compute unit for an FP32 or FP64 streaming step (work-groups of `threads`
+// lanes, one cell each, q pulls of `bytes` per cell): the count that keeps about 78 KiB of pulls
+// in flight per compute unit, and at least 8 waves. Measured best caps for 256-lane work-groups
+// (D3Q19 and D3Q27 256^3, D2Q9 256 x 65536): D3Q19 FP32 4, D3Q19 FP64 2, D3Q27 FP32 3, D3Q27
+// FP64 2 (1 is far slower), D2Q9 FP64 4; D2Q9 FP32 gains nothing from a cap (the rule gives 9,
+// more than fit).
+constexpr unsigned stream_groups(unsigned q, unsigned bytes, unsigned threads = 256u)
 {
-    const unsigned per = 256u * q * bytes;
+    const unsigned per = threads * q * bytes;
     const unsigned n = (79872u + per / 2u) / per;
-    return n < 2u ? 2u : n;
+    const unsigned least = (8u * 64u + threads - 1u) / threads;
+    return n < least ? least : n;
 }
-constexpr unsigned stream_lds(unsigned q, unsigned bytes)
+// The LDS to reserve for that cap, or 0 where the cap is no lower than the most work-groups of
+// that size a compute unit holds (32 waves).
+constexpr unsigned stream_lds(unsigned q, unsigned bytes, unsigned threads = 256u)
 {
-    return stream_groups(q, bytes) >= 8u ? 0u : cap_lds(stream_groups(q, bytes));
+    const unsigned most = 32u / ((threads + 63u) / 64u);
+    return stream_groups(q, bytes, threads) >= most ? 0u : cap_lds(stream_groups(q, bytes, threads));
 }
 static_assert(stream_groups(19, 4) == 4 && stream_groups(19, 8) == 2 && stream_groups(27, 4) == 3 &&
-                  stream_groups(27, 8) == 2 && stream_groups(9, 8) == 4 && stream_lds(9, 4) == 0,
-              "the measured caps");
+                  stream_groups(27, 8) == 2 && stream_groups(9, 8) == 4 && stream_lds(9, 4) == 0 &&
+                  stream_groups(19, 4, 64) == 16 && stream_groups(27, 8, 64) == 8,
+              "the measured caps, and the same bytes in flight for smaller work-groups");
 
 constexpr int kPartials = 5;
 constexpr uint32_t kMomentGroups = 2048;  // most work-groups of a moments launch

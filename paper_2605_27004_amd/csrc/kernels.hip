@@ -1094,11 +1094,14 @@ hipError_t launch_init(int lattice, int storage, int order, const Grid &g, const
 // The FP32 links step (80 VGPRs, 6 resident) at 4 per CU: 4,962 -> 4,851 us on the 512^3
 // porous medium (3: 4,890, 5: 4,882), where the extra work-groups re-fetched lines. Rows longer
 // than a work-group (shifted pulls), FP32 at 4 per CU: 512^3 3,388 -> 3,339 us, 384^3 unchanged.
-template <int LAT, typename S, int M> constexpr unsigned step_lds()
+template <int LAT, typename S, int M> unsigned step_lds(unsigned threads)
 {
     constexpr bool f32 = std::is_same<S, float>::value, f64 = std::is_same<S, double>::value;
-    if (M == kLinks) return f32 ? cap_lds(4) : 0u;
-    if (M == kPlain || M == kStream) return (f32 || f64) ? stream_lds(Lattice<LAT>::Q, sizeof(S)) : 0u;
+    if (M == kLinks) {  // 4 work-groups of 256 lanes, the same lanes in smaller work-groups
+        const unsigned n = 4u * 256u / threads, most = 32u / ((threads + 63u) / 64u);
+        return f32 && n < most ? cap_lds(n) : 0u;
+    }
+    if (M == kPlain || M == kStream) return (f32 || f64) ? stream_lds(Lattice<LAT>::Q, sizeof(S), threads) : 0u;
     return 0u;
 }
 
@@ -1114,6 +1117,7 @@ hipError_t launch_step(int lattice, int storage, int order, const Grid &g, const
             const StepConsts<C> *kc;
             if constexpr (sizeof(C) == 8) kc = &k64; else kc = &k32;
             const dim3 g3 = cell_grid(g, block_x, block_y), block(block_x, block_y);
+            const unsigned threads = (unsigned)(block_x * block_y);
             TileMap m;
             m.tiles_x = g3.x;
             m.tiles_y = g3.y;
@@ -1131,12 +1135,12 @@ hipError_t launch_step(int lattice, int storage, int order, const Grid &g, const
     do {                                                                                                         \
         if constexpr (M != kLinks) {                                                                             \
             if (aligned) {                                                                                       \
-                hipLaunchKernelGGL((k_step<LAT, S, O, M, kPullRows>), grid, block, (step_lds<LAT, S, M>()),  \
+                hipLaunchKernelGGL((k_step<LAT, S, O, M, kPullRows>), grid, block, (step_lds<LAT, S, M>(threads)),  \
                                    stream, in, out, g, *kc, m, links, gray);                                     \
                 break;                                                                                           \
             }                                                                                                    \
         }                                                                                                        \
-        hipLaunchKernelGGL((k_step<LAT, S, O, M, kPullShifted>), grid, block, (step_lds<LAT, S, M>()), stream, in, out, g, \
+        hipLaunchKernelGGL((k_step<LAT, S, O, M, kPullShifted>), grid, block, (step_lds<LAT, S, M>(threads)), stream, in, out, g, \
                            *kc, m, links, gray);                                                                 \
     } while (0)
             if (mode == kStream) {
