@@ -138,10 +138,11 @@ def test_adjoint_matches_gpu_finite_differences_no_force():
     assert abs(dt[0][1] - fd) <= 1e-6 * abs(fd) + 1e-9 * abs(j)
 
 
-def test_multi_row_adjoint_launch_matches_gpu_finite_differences():
-    """A grid large enough that each adjoint work-group takes several rows (70 x 130 x 67: 4355
-    rows of 128 x 2 tiles, 2 per work-group, the last one alone), with force, gray cells and
-    the flux objective: the FP64 gradient against central differences of the FP64 forward."""
+def test_adjoint_launch_over_many_row_tiles_matches_gpu_finite_differences():
+    """A grid of many adjoint work-groups (70 x 130 x 67: 65 row tiles of 128 x 2 per z-plane,
+    4355 work-groups in a one-dimensional launch, every tile ragged in x and the last one of each
+    plane in y), with force, gray cells and the flux objective: the FP64 gradient against central
+    differences of the FP64 forward."""
     c = _case("D3Q19", (70, 130, 67), seed=9)
     steps, ckpt, plane = 12, 5, 69
     gray = c["gray"].astype(np.float32)
@@ -165,13 +166,13 @@ def test_multi_row_adjoint_launch_matches_gpu_finite_differences():
 
     h = 1e-4
     fd = (J(c["tensor"], c["tau"] + h) - J(c["tensor"], c["tau"] - h)) / (2 * h)
-    print(f"[grad] multi-row dtau {du:.9e} fd {fd:.9e}", flush=True)
+    print(f"[grad] many-tile dtau {du:.9e} fd {fd:.9e}", flush=True)
     assert abs(du - fd) <= 1e-5 * abs(fd) + 1e-9 * abs(j)
     h = 1e-5
     tp = c["tensor"].copy(); tm = c["tensor"].copy()
     tp[1, 2] += h; tp[2, 1] += h; tm[1, 2] -= h; tm[2, 1] -= h
     fd = (J(tp, c["tau"]) - J(tm, c["tau"])) / (2 * h)
-    print(f"[grad] multi-row dT_yz {dt[1][2]:.9e} fd {fd:.9e}", flush=True)
+    print(f"[grad] many-tile dT_yz {dt[1][2]:.9e} fd {fd:.9e}", flush=True)
     assert abs(dt[1][2] - fd) <= 1e-5 * abs(fd) + 1e-9 * abs(j)
 
 
