@@ -140,9 +140,9 @@ def test_adjoint_matches_gpu_finite_differences_no_force():
 
 def test_adjoint_launch_over_many_row_tiles_matches_gpu_finite_differences():
     """A grid of many adjoint work-groups (70 x 130 x 67: 65 row tiles of 128 x 2 per z-plane,
-    4355 work-groups in a one-dimensional launch, every tile ragged in x and the last one of each
-    plane in y), with force, gray cells and the flux objective: the FP64 gradient against central
-    differences of the FP64 forward."""
+    4355 work-groups in a one-dimensional launch, every tile ragged in x: 70 of its 128 lanes),
+    with force, gray cells and the flux objective: the FP64 gradient against central differences
+    of the FP64 forward."""
     c = _case("D3Q19", (70, 130, 67), seed=9)
     steps, ckpt, plane = 12, 5, 69
     gray = c["gray"].astype(np.float32)
