@@ -660,6 +660,14 @@ template <typename S> __device__ inline S ld_slot(const S *base, const Grid &g, 
     slot_at(base, g, s, p, idx);
     return ld_at(p, idx);
 }
+// The same through a non-temporal load (data read once per launch).
+template <typename S> __device__ inline S ld_slot_nt(const S *base, const Grid &g, const Slot &s)
+{
+    const S *p;
+    uint32_t idx;
+    slot_at(base, g, s, p, idx);
+    return ld_nt_at(p, idx);
+}
 template <typename S> __device__ inline void st_slot(S *base, const Grid &g, const Slot &s, S v)
 {
     S *p;

@@ -843,16 +843,18 @@ __device__ inline void adjoint_cell(const S *__restrict__ state, const typename 
     if (LINKS && inside && (lk & 1u)) {
         // a solid cell holds no state: its adjoint is zero and it adds no sensitivity
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i) st_plane_aux<0>(out, i, C(0));
+        for (int i = 0; i < L::Q; ++i) st_plane(out, i, C(0));
     } else if (inside) {
         // forward quantities at x (the canonical gather, bounce-back slots included)
         C gp[NP + 1], gm[NP + 1];
-        gp[0] = Conv<S>::ld(ld_pop(state, g, 0, own_ref(c)));
+        // every input and output of a reverse step is touched once per launch: non-temporal loads
+        // and stores (D3Q19 FP32 128^3: 94.5 -> 86.4-88.3 us against cached ones)
+        gp[0] = Conv<S>::ld(ld_nt_at(pop_base(state, g, 0, own_ref(c)), own_ref(c).idx));
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
             const Slot sp = slot_plus<LAT>(c, p, lk), sm = slot_minus<LAT>(c, p, lk);
-            gp[p + 1] = Conv<S>::ld(ld_slot(state, g, sp));
-            gm[p + 1] = Conv<S>::ld(ld_slot(state, g, sm));
+            gp[p + 1] = Conv<S>::ld(ld_slot_nt(state, g, sp));
+            gm[p + 1] = Conv<S>::ld(ld_slot_nt(state, g, sm));
         }
         C drho, jx, jy, jz;
         moments_of<LAT>(gp, gm, drho, jx, jy, jz);
@@ -862,12 +864,12 @@ __device__ inline void adjoint_cell(const S *__restrict__ state, const typename 
         // adjoint of the post-collision populations: mu_k(x) = lam_k(t+1, x + c_k), or, when
         // x + c_k is solid (halfway bounce-back), lam_opp(k)(t+1, x)
         C mup[NP + 1], mum[NP + 1];
-        mup[0] = ld_pop(lam_in, g, 0, own_ref(c));
+        mup[0] = ld_nt_at(pop_base(lam_in, g, 0, own_ref(c)), own_ref(c).idx);
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
             const Slot ap = adjoint_slot_plus<LAT>(c, p, lk), am = adjoint_slot_minus<LAT>(c, p, lk);
-            mup[p + 1] = ld_slot(lam_in, g, ap);
-            mum[p + 1] = ld_slot(lam_in, g, am);
+            mup[p + 1] = ld_slot_nt(lam_in, g, ap);
+            mum[p + 1] = ld_slot_nt(lam_in, g, am);
         }
         const C mg = gray ? (C)gray[c.own] : C(0);
         const C keep = C(1) - mg;  // nu_k = keep * mu_k
@@ -904,7 +906,7 @@ __device__ inline void adjoint_cell(const S *__restrict__ state, const typename 
         // nu_k - nu_0 and mu_k - mu_0 (the rest direction then adds nothing)
         dtau = C(0);
         dm = C(0);
-        st_plane_aux<0>(out, 0, fmad(mg, mup[0], fmad(om, nm.ref, base)));
+        st_plane(out, 0, fmad(mg, mup[0], fmad(om, nm.ref, base)));
 #pragma unroll
         for (int p = 0; p < NP; ++p) {
             C ep, em;
@@ -926,8 +928,8 @@ __device__ inline void adjoint_cell(const S *__restrict__ state, const typename 
             }
             const PairRow v = L::pair(p);
             const C vc = (C)v.cx * ax + (C)v.cy * ay + (C)v.cz * az;
-            st_plane_aux<0>(out, 2 * p + 1, fmad(mg, mum[p + 1], fmad(om, keep * mup[p + 1], base + vc)));
-            st_plane_aux<0>(out, 2 * p + 2, fmad(mg, mup[p + 1], fmad(om, keep * mum[p + 1], base - vc)));
+            st_plane(out, 2 * p + 1, fmad(mg, mum[p + 1], fmad(om, keep * mup[p + 1], base + vc)));
+            st_plane(out, 2 * p + 2, fmad(mg, mup[p + 1], fmad(om, keep * mum[p + 1], base - vc)));
             dm = fmad(mup[p + 1] - mup[0], gm[p + 1] - bp, dm);
             dm = fmad(mum[p + 1] - mup[0], gp[p + 1] - bm, dm);
         }
