@@ -221,19 +221,12 @@ template <typename S> __device__ inline void st_at(S *p, uint32_t idx, S v)
 {
     *reinterpret_cast<S *>(reinterpret_cast<char *>(p) + (uint32_t)(idx * (uint32_t)sizeof(S))) = v;
 }
-// Streaming store of the step's output: it is not read again within the step, and keeping it
-// out of the caches leaves them to the x-boundary lines the pulls share (measured faster; the
-// loads themselves stay cached for that reason).
-template <typename S> __device__ inline void st_stream(S *p, uint32_t idx, S v)
-{
-    __builtin_nontemporal_store(v, reinterpret_cast<S *>(reinterpret_cast<char *>(p) + (uint32_t)(idx * (uint32_t)sizeof(S))));
-}
-
 // Streaming stores of one cell's q populations through a buffer resource based at the cell's
 // z-plane: all q stores share the lane's byte offset and differ by a work-group-uniform offset
 // (direction i at i blocks-per-direction), so they need no per-lane address arithmetic. Offsets
-// stay below 4 GiB because one z-plane of populations does. Cache policy: non-temporal, as
-// st_stream.
+// stay below 4 GiB because one z-plane of populations does. Cache policy: non-temporal. A step's
+// output is not read again within the step, and keeping it out of the caches leaves them to the
+// lines the shifted pulls share (measured faster; those loads stay cached for that reason).
 struct PlaneStores {
     __amdgpu_buffer_rsrc_t rsrc;
     uint32_t lane_off;    // bytes from the z-plane base to direction 0 of the cell
@@ -314,10 +307,6 @@ template <int CTRL> __device__ inline double wave_shift(double edge, double v)
 template <typename S> __device__ inline void st_pop(S *base, const Grid &g, int i, const Ref &r, S v)
 {
     st_at(pop_base(base, g, i, r), r.idx, v);
-}
-template <typename S> __device__ inline void st_pop_stream(S *base, const Grid &g, int i, const Ref &r, S v)
-{
-    st_stream(pop_base(base, g, i, r), r.idx, v);
 }
 
 // Issue order of a cell's q pulls: by source z-plane (z - 1, z, z + 1), then by direction
